@@ -1,0 +1,122 @@
+"""Emulated mixed-precision tile Cholesky (oracle side).
+
+The paper's "Discussion and Future Work" section names the method: tiled
+matrix algorithms in which tiles of one matrix are held at different
+precisions (16, 32 and 64 bit).  This module writes that method out with the
+textbook right-looking tile Cholesky (POTRF on the diagonal tile, TRSM on the
+panel below it, SYRK/GEMM on the trailing tiles) and these readings:
+
+* the tile map p(i, j) gives each lower tile its storage format; the diagonal
+  tiles are FP64 (the diagonal POTRF, the log-determinant and the SYRK into the
+  diagonal stay in FP64);
+* Sigma's tiles are rounded ONCE from FP64 to their format before step 0;
+* POTRF of A_kk in FP64; TRSM  A_ik <- round_{p(i,k)}(A_ik L_kk^{-T}) with the
+  solve done in FP64 on the widened operands and one rounding at the end;
+* SYRK  A_jj <- A_jj - L_jk L_jk^T in FP64;
+* GEMM  A_ij <- round_p(A_ij - round_p(L_ik) round_p(L_jk)^T), p = p(i,j): the
+  update runs in the output tile's format (operands converted to it on load),
+  the product is accumulated exactly (FP64 model) and the result is rounded
+  once to p;
+* n that is not a multiple of nb is padded with an identity block, which
+  leaves the log-determinant and the solution of the leading block unchanged.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .dense import NotPositiveDefinite, cholesky_lower, forward_substitution
+from .fpformat import CODE, fmt_of, round_to
+
+FP64_CODE = CODE["fp64"]
+UNUSED = 255
+
+
+def num_tiles(n: int, nb: int) -> int:
+    return (n + nb - 1) // nb
+
+
+def tilemap_uniform(n: int, nb: int, fmt="fp64") -> np.ndarray:
+    nt = num_tiles(n, nb)
+    m = np.full((nt, nt), UNUSED, dtype=np.uint8)
+    code = CODE[fmt_of(fmt).name]
+    for i in range(nt):
+        for j in range(i + 1):
+            m[i, j] = FP64_CODE if i == j else code
+    return m
+
+
+def tilemap_banded(n: int, nb: int, bands) -> np.ndarray:
+    """Map from bands [(d_max, fmt), ..., (None, fmt)]: tile (i, j), i >= j,
+    with distance d = i - j gets the format of the first band whose d_max >= d.
+    The diagonal (d = 0) must fall in an FP64 band."""
+    nt = num_tiles(n, nb)
+    m = np.full((nt, nt), UNUSED, dtype=np.uint8)
+    for i in range(nt):
+        for j in range(i + 1):
+            d = i - j
+            for dmax, f in bands:
+                if dmax is None or d <= dmax:
+                    m[i, j] = CODE[fmt_of(f).name]
+                    break
+    if any(m[i, i] != FP64_CODE for i in range(nt)):
+        raise ValueError("diagonal tiles must be FP64")
+    return m
+
+
+def pad_identity(A: np.ndarray, N: int) -> np.ndarray:
+    n = A.shape[0]
+    P = np.eye(N)
+    P[:n, :n] = A
+    return P
+
+
+def flops_by_format(nt: int, nb: int, tmap: np.ndarray) -> dict:
+    """Algorithmic flops of the tile factorisation split by the format the
+    step computes in: POTRF nb^3/3, TRSM nb^3, SYRK nb^3 (all FP64), GEMM
+    2 nb^3 in the output tile's format."""
+    out = {}
+    def add(code, v):
+        out[code] = out.get(code, 0.0) + v
+    for k in range(nt):
+        add(FP64_CODE, nb ** 3 / 3.0)
+        for i in range(k + 1, nt):
+            add(FP64_CODE, float(nb) ** 3)        # TRSM
+            add(FP64_CODE, float(nb) ** 3)        # SYRK into (i, i)
+            for j in range(k + 1, i):
+                add(int(tmap[i, j]), 2.0 * nb ** 3)
+    return out
+
+
+def tile_cholesky_emulated(Sigma: np.ndarray, nb: int, tmap: np.ndarray):
+    """Returns dict(L, info, N) where L is the N x N lower factor (padded size)
+    holding the stored tile values widened to float64; info is 0 or the 1-based
+    global column of the first non-positive pivot."""
+    n = Sigma.shape[0]
+    nt = num_tiles(n, nb)
+    N = nt * nb
+    A = pad_identity(np.asarray(Sigma, dtype=np.float64), N)
+    T = lambda i, j: (slice(i * nb, (i + 1) * nb), slice(j * nb, (j + 1) * nb))
+    p = lambda i, j: int(tmap[i, j])
+    for i in range(nt):
+        if p(i, i) != FP64_CODE:
+            raise ValueError("diagonal tiles must be FP64")
+        for j in range(i):
+            A[T(i, j)] = round_to(A[T(i, j)], p(i, j))
+    for k in range(nt):
+        try:
+            Lkk = cholesky_lower(A[T(k, k)])
+        except NotPositiveDefinite as e:
+            return dict(L=np.tril(A), info=k * nb + e.info, N=N)
+        A[T(k, k)] = Lkk
+        for i in range(k + 1, nt):
+            # X L_kk^T = A_ik  <=>  L_kk X^T = A_ik^T
+            X = forward_substitution(Lkk, A[T(i, k)].T).T
+            A[T(i, k)] = round_to(X, p(i, k))
+        for j in range(k + 1, nt):
+            Ljk = A[T(j, k)]
+            A[T(j, j)] = A[T(j, j)] - Ljk @ Ljk.T
+            for i in range(j + 1, nt):
+                f = p(i, j)
+                upd = round_to(A[T(i, k)], f) @ round_to(Ljk, f).T
+                A[T(i, j)] = round_to(A[T(i, j)] - upd, f)
+    return dict(L=np.tril(A), info=0, N=N)
