@@ -1,0 +1,244 @@
+"""Benchmark: mixed-precision tile Cholesky + solve + Gaussian log-likelihood.
+
+Workload (the mixed-precision tile Cholesky configuration): n = 32768 sites
+drawn uniformly in the unit square, Matern nu = 3/2 covariance (variance 1,
+range 0.05, nugget 1e-6), tiles nb = 512, 16 N(0,1) observation vectors,
+FP64 iterative refinement (PCG) to ||r||_2/||b||_2 <= 1e-9, log-likelihood.
+
+One step = one mpcr_gauss_loglik call: Morton ordering, covariance
+generation into the tile formats, the tile factorisation, log-determinant,
+refined solve and the log-likelihood, all on the GPU with inputs resident in
+HBM.  `value` is the algorithmic rate (n^3/3 + 2 n^2 nrhs) / step time of the
+mixed path; the all-FP64 path is timed the same way for the speed-up.
+
+Precision map: the band map (FP64 for tile distance d <= 2, FP32 for
+3 <= d <= 8, BF16 beyond) breaks down on this covariance (the BF16-stored
+far tiles make the matrix indefinite); the library reports NOT_SPD for it
+and the bench records that outcome.  The timed mixed path uses the same
+band map promoted tile by tile by the norm guard u_p * max|Sigma_tile| <=
+0.1 * nugget (mpcr_tilemap_guarded).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2516.6, 3: 2516.6, 4: 5033.2}
+FMT_NAME = {0: "fp64", 1: "fp32", 2: "fp16", 3: "bf16", 4: "fp8_e4m3"}
+KIND_NAME = {0: "tile_update_fp64", 1: "tile_update_fp32", 2: "tile_update_fp16", 3: "tile_update_bf16",
+             4: "tile_update_fp8", 5: "potrf_fp64", 6: "trsm_fp64"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=None, help="override the order (smaller runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=8192)
+    return ap.parse_args()
+
+
+class Lib:
+    def __init__(self, torch):
+        from paper_2406_02701_amd import mpcr
+        self.m = mpcr
+        self.torch = torch
+
+    def ctx(self):
+        c = ctypes.c_void_p()
+        s = self.torch.cuda.current_stream().cuda_stream
+        self.m.check(self.m.mpcr_ctx_create(0, ctypes.c_void_p(s), ctypes.byref(c)))
+        return c
+
+    def loglik(self, ctx, n, dl, dz, nrhs, th, hmap, nb, opts):
+        out = np.zeros(nrhs)
+        diag = self.m.mpcr_diag_t()
+        tm = self.m.tilemap(n, nb, hmap)
+        st = self.m.mpcr_gauss_loglik(ctx, n, dl.data_ptr(), dz.data_ptr(), nrhs, ctypes.byref(th),
+                                      ctypes.byref(tm), 1, None if opts is None else ctypes.byref(opts),
+                                      self.m.f64p(out), ctypes.byref(diag))
+        return st, out, diag
+
+    def stats(self, ctx, kind):
+        ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self.m.check(self.m.mpcr_ctx_kernel_stats(ctx, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
+        return ms.value, n.value, fl.value
+
+
+def banded(mp, n, nb, dmax, precs):
+    nt = (n + nb - 1) // nb
+    out = np.zeros((nt, nt), np.uint8)
+    st = mp.mpcr_tilemap_banded(n, nb, (ctypes.c_int * len(dmax))(*dmax), (ctypes.c_int * len(precs))(*precs),
+                                len(dmax), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    mp.check(st)
+    return out
+
+
+def timed_steps(lib, ctx, args, call):
+    torch = lib.torch
+    for _ in range(args.warmup):
+        st, out, diag = call()
+        lib.m.check(st, ctx)
+    lib.m.mpcr_ctx_reset_stats(ctx)
+    lib.m.mpcr_ctx_set_profiling(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, out, diag = call()
+        lib.m.check(st, ctx)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    lib.m.mpcr_ctx_set_profiling(ctx, 0)
+    return dt, out, diag
+
+
+def cpu_baseline(w, n_cpu):
+    """The FP64 oracle (dense Cholesky, forward/backward solves, log-likelihood)
+    on the first n_cpu sites of the same recipe."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import loglik
+    locs = synth.locations(w["n"], w["seed_locs"])[:n_cpu]
+    z = synth.normal_rhs(w["n"], w["nrhs"], w["seed_z"])[:n_cpu]
+    lo, zo, _ = loglik.order_sites(locs, z)
+    t0 = time.perf_counter()
+    loglik.loglik_plain(lo, zo, w["sigma2"], w["range"], w["nu"], w["nugget"])
+    dt = time.perf_counter() - t0
+    flops = n_cpu ** 3 / 3 + 2 * n_cpu ** 2 * w["nrhs"]
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"plain FP64 oracle log-likelihood on the first {n_cpu} sites of the workload "
+                      f"({w['nrhs']} RHS), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    lib = Lib(torch)
+    mp = lib.m
+    w = dict(synth.WORKLOADS["mixed_n32768"])
+    if args.n:
+        w["n"] = args.n
+    n, nb, nrhs = w["n"], w["nb"], w["nrhs"]
+    locs = synth.locations(n, w["seed_locs"])
+    z = synth.normal_rhs(n, nrhs, w["seed_z"])
+    dl = torch.from_numpy(np.ascontiguousarray(locs.T)).cuda()
+    dz = torch.from_numpy(np.ascontiguousarray(z.T)).cuda()
+    th = mp.mpcr_theta_t(w["sigma2"], w["range"], w["nu"], w["nugget"])
+    opts = mp.mpcr_refine_opts_t(1e-9, 200, 0, 20, 0)
+    flops = n ** 3 / 3 + 2 * n ** 2 * nrhs
+
+    # maps: literal band map, its norm-guarded version, and all-FP64
+    lit = banded(mp, n, nb, [2, 8, -1], [0, 1, 3])
+    ctx_m = lib.ctx()
+    # the guard needs max|Sigma| per tile of the Morton-ordered covariance
+    perm = torch.zeros(n, dtype=torch.int64, device="cuda")
+    mp.check(mp.mpcr_morton_order(ctx_m, n, dl.data_ptr(), perm.data_ptr()), ctx_m)
+    dl_sorted = torch.from_numpy(np.ascontiguousarray(locs[perm.cpu().numpy()].T)).cuda()
+    nt = lit.shape[0]
+    amax = np.zeros((nt, nt))
+    mp.check(mp.mpcr_covariance_tile_amax(ctx_m, n, nb, dl_sorted.data_ptr(), ctypes.byref(th), mp.f64p(amax)), ctx_m)
+    guarded = np.zeros_like(lit)
+    mp.check(mp.mpcr_tilemap_guarded(n, nb, lit.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), mp.f64p(amax),
+                                     0.1 * w["nugget"], guarded.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    fp64map = banded(mp, n, nb, [-1], [0])
+
+    # literal band map outcome (untimed)
+    st, _, dlit = lib.loglik(ctx_m, n, dl, dz, nrhs, th, lit, nb, opts)
+    literal = {"status": mp.STATUS_NAMES.get(st, st), "info": int(dlit.info)}
+
+    # mixed path (guarded map), timed
+    t_mix, ll_mix, d_mix = timed_steps(lib, ctx_m, args, lambda: lib.loglik(ctx_m, n, dl, dz, nrhs, th, guarded,
+                                                                          nb, opts))
+    kstats = {k: lib.stats(ctx_m, k) for k in range(7)}
+    # all-FP64 path (paper's evaluation: forward solve quad), timed on its own context
+    ctx_d = lib.ctx()
+    t_64, ll_64, d_64 = timed_steps(lib, ctx_d, args, lambda: lib.loglik(ctx_d, n, dl, dz, nrhs, th, fp64map, nb,
+                                                                         None))
+    kstats64 = {k: lib.stats(ctx_d, k) for k in range(7)}
+
+    # dominant kernel of the mixed step (largest total time) and its roofline
+    dom = max(range(7), key=lambda k: kstats[k][0])
+    ms, launches, kfl = kstats[dom]
+    avg_ms = ms / max(launches, 1)
+    fl_per_launch = kfl / max(launches, 1)
+    achieved = fl_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[dom] if dom <= 4 else PEAK_TFLOPS[0]
+    roofline = {"bound": "mfma", "kernel": KIND_NAME[dom], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "launches": launches, "avg_launch_ms": avg_ms,
+                "flops_per_launch": fl_per_launch}
+
+    fl_by = list(d_mix.flops_by_prec)
+    tot = sum(fl_by)
+    share = {FMT_NAME[p]: fl_by[p] / tot for p in range(5) if fl_by[p] > 0}
+    ideal_s = sum(fl_by[p] / (PEAK_TFLOPS[p] * 1e12) for p in range(5))
+    ideal64 = sum(d_64.flops_by_prec) / (PEAK_TFLOPS[0] * 1e12)
+
+    line = {
+        "metric": "tile-Cholesky+solve TFLOP/s mixed vs FP64 at <=1e-9 residual",
+        "value": flops / t_mix / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mix * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed-f64/f32/bf16",
+        "data": "synthetic",
+        "config": {"workload": "mixed_n32768" if n == 32768 else f"mixed_n{n}", "n": n, "nb": nb, "nrhs": nrhs,
+                   "nu": w["nu"], "sigma2": w["sigma2"], "range": w["range"], "nugget": w["nugget"],
+                   "map": "band d<=2 fp64 / 3-8 fp32 / >=9 bf16, norm-guarded (u_p max|tile| <= 0.1 nugget)",
+                   "refine": "pcg, ||r||_2/||b||_2 <= 1e-9"},
+        "fp64_path": {"value": flops / t_64 / 1e12, "ms_per_step": t_64 * 1e3, "eta": d_64.eta,
+                      "rel_resid2": d_64.rel_resid2, "logdet": d_64.logdet,
+                      "t_factor_ms": d_64.t_factor_ms, "t_solve_ms": d_64.t_solve_ms,
+                      "ideal_ms_at_mfma_peak": ideal64 * 1e3},
+        "speedup_vs_fp64": t_64 / t_mix,
+        "mixed": {"eta": d_mix.eta, "rel_resid2": d_mix.rel_resid2, "iters": d_mix.iters,
+                  "converged": bool(d_mix.converged), "logdet": d_mix.logdet,
+                  "logdet_rel_err_vs_fp64": abs(d_mix.logdet - d_64.logdet) / abs(d_64.logdet),
+                  "loglik_rel_err_vs_fp64": float(np.max(np.abs(ll_mix - ll_64) / np.abs(ll_64))),
+                  "t_gen_ms": d_mix.t_gen_ms, "t_factor_ms": d_mix.t_factor_ms, "t_solve_ms": d_mix.t_solve_ms,
+                  "t_refine_ms": d_mix.t_refine_ms, "flop_share": share, "ideal_ms_at_mfma_peak": ideal_s * 1e3,
+                  "tiles_by_format": {FMT_NAME[p]: int(np.sum(guarded[np.tril_indices(nt)] == p))
+                                      for p in range(5) if np.any(guarded[np.tril_indices(nt)] == p)}},
+        "literal_band_map": literal,
+        "kernels_mixed": {KIND_NAME[k]: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
+                                         "tflops": (v[2] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0}
+                          for k, v in kstats.items() if v[1]},
+        "kernels_fp64": {KIND_NAME[k]: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
+                                        "tflops": (v[2] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0}
+                         for k, v in kstats64.items() if v[1]},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    mp.mpcr_ctx_destroy(ctx_m)
+    mp.mpcr_ctx_destroy(ctx_d)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_n, n))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,281 @@
+/*
+ * mpcr.h -- C interface of the MI355X (gfx950) mixed-precision tile Cholesky /
+ * Gaussian log-likelihood library.
+ *
+ * The operations follow the paper "MPCR: Multi-Precision Computations Package
+ * in R" (arXiv 2406.02701):
+ *   - matrix product C = op(A) op(B) in 64-, 32- or 16-bit precision, with the
+ *     result in the highest input precision (section "Operations on MPCR
+ *     objects"; section "Linear Algebra Functions Performance");
+ *   - Cholesky factorisation, forward/backward triangular solves, the
+ *     log-determinant 2 sum log L_ii and the quadratic form ||L^{-1} z||^2 that
+ *     give the Gaussian log-likelihood of a Matern covariance (section "Maximum
+ *     Likelihood Estimation of Matern Covariance Function");
+ *   - the tiled algorithm that holds tiles of one matrix at different
+ *     precisions (section "Discussion and Future Work"), with FP64 refinement
+ *     (multi-precision stages, section "Introduction").
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major with a leading dimension (the paper's objects
+ *     store elements column by column, section "Creating MPCR objects").
+ *   - Pointers named d_* are DEVICE pointers owned by the caller (typically
+ *     torch tensors); h_* are host pointers.  The library never frees caller
+ *     memory.  The library allocates device memory only inside a factor
+ *     (released by mpcr_factor_destroy) or in a context's workspace (released
+ *     by mpcr_ctx_destroy).
+ *   - Work is ordered on the context's HIP stream.  Calls that return host
+ *     values (info, loglik, diag) synchronise that stream before returning.
+ *   - Errors are returned as mpcr_status_t codes, never thrown; the text of
+ *     the last error of a context is available from mpcr_last_error().
+ *   - info follows LAPACK: 0 = success, k > 0 = the leading minor of order k
+ *     (global 1-based column) is not positive definite.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef MPCR_H
+#define MPCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage / compute formats.  FP64, FP32 and FP16 are the IEEE formats the
+ * paper describes (section "Floating-Point Arithmetic in Modern Technology");
+ * BF16 (1/8/7) and FP8-E4M3FN (1/4/3, no infinities, largest finite 448,
+ * conversions saturate) are the two further low formats of the tile map. */
+typedef enum {
+  MPCR_FP64 = 0,
+  MPCR_FP32 = 1,
+  MPCR_FP16 = 2,
+  MPCR_BF16 = 3,
+  MPCR_FP8_E4M3 = 4
+} mpcr_prec_t;
+
+typedef enum {
+  MPCR_OK = 0,
+  MPCR_ERR_ARG = -1,            /* invalid argument (shape, pointer, format, option) */
+  MPCR_ERR_NOT_SPD = -2,        /* factorisation met a non-positive pivot; see info */
+  MPCR_ERR_NOT_CONVERGED = -3,  /* refinement reached max_iter above tolerance */
+  MPCR_ERR_NOMEM = -4,          /* device allocation failed */
+  MPCR_ERR_DEVICE = -5,         /* a HIP call failed */
+  MPCR_ERR_REJECTED = -6        /* request does not fit the serving budget */
+} mpcr_status_t;
+
+typedef struct mpcr_ctx mpcr_ctx;
+typedef struct mpcr_factor mpcr_factor;
+
+/* Per-tile precision map of an n x n symmetric matrix cut into nt x nt tiles of
+ * nb x nb (nt = ceil(n / nb); the last tile row/column is padded with an
+ * identity block).  h_map is a HOST array of nt*nt bytes, row-major over tile
+ * indices (i, j); only entries with i >= j are read and each holds an
+ * mpcr_prec_t.  Diagonal tiles must be MPCR_FP64 (the diagonal POTRF, the SYRK
+ * into it and the log-determinant stay in FP64). */
+typedef struct {
+  int64_t n;
+  int64_t nb;
+  int64_t nt;
+  const uint8_t* h_map;
+} mpcr_tilemap_t;
+
+/* Matern covariance parameters: Sigma_ij = sigma2 * m_nu(||s_i - s_j|| / range)
+ * + nugget * [i == j], with m_nu the half-integer closed form of
+ * x^nu K_nu(x) / (2^(nu-1) Gamma(nu)) (MLE section of the paper); nu must be
+ * 0.5, 1.5 or 2.5. */
+typedef struct {
+  double sigma2;
+  double range;
+  double nu;
+  double nugget;
+} mpcr_theta_t;
+
+/* Refinement of Sigma x = b with the (mixed-precision) factor L~ as
+ * preconditioner M = L~ L~^T; residuals and vectors in FP64.
+ *   tol          stop when every column's normwise backward error
+ *                eta = ||r||_inf / (||Sigma||_inf ||x||_inf + ||b||_inf) <= tol
+ *                (||r||_2/||b||_2 is reported as well)
+ *   max_iter     iteration cap (0 = no refinement: x = M^{-1} b)
+ *   solver       0 = preconditioned conjugate gradients, 1 = classical
+ *                iterative refinement x <- x + M^{-1} r
+ *   recompute    PCG recomputes the true residual every `recompute` steps */
+typedef struct {
+  double tol;
+  int max_iter;
+  int solver;
+  int recompute;
+  int reserved;
+} mpcr_refine_opts_t;
+
+/* Diagnostics filled by mpcr_potrs / mpcr_gauss_loglik (host struct). */
+typedef struct {
+  int iters;              /* refinement iterations taken */
+  int converged;          /* 1 if every column met the stopping rule */
+  double eta;             /* max over columns of the normwise backward error */
+  double rel_resid2;      /* max over columns of ||b - Sigma x||_2 / ||b||_2 */
+  double logdet;          /* log|Sigma| from the factor's diagonal tiles */
+  double quad0;           /* first column's quadratic form z^T Sigma^{-1} z */
+  int64_t info;           /* LAPACK-style info of the factorisation */
+  double t_gen_ms, t_factor_ms, t_solve_ms, t_refine_ms;  /* phase times (HIP events) */
+  double flops_by_prec[5];  /* algorithmic factorisation flops by compute format */
+} mpcr_diag_t;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the device's default stream).  *out receives the
+ * context.  Errors: MPCR_ERR_ARG (out NULL, bad device), MPCR_ERR_DEVICE. */
+int mpcr_ctx_create(int device, void* hip_stream, mpcr_ctx** out);
+int mpcr_ctx_destroy(mpcr_ctx* ctx);
+/* Text of the context's last error ("" if none).  Valid until the next call. */
+const char* mpcr_last_error(const mpcr_ctx* ctx);
+/* Library version string, e.g. "mpcr 0.1 gfx950". */
+const char* mpcr_version(void);
+
+/* Kernel timing of a context.  With profiling on, every tile-factorisation
+ * launch queued by this context is bracketed by two HIP events recorded on the
+ * context's stream; elapsed times are accumulated when the call synchronises.
+ * Kinds: 0..4 = tile GEMM/SYRK update computed in format MPCR_FP64..FP8,
+ * 5 = diagonal POTRF, 6 = panel TRSM.  mpcr_ctx_kernel_stats returns, for one
+ * kind, the total milliseconds, the number of launches and the algorithmic
+ * flops those launches performed (2 nb^3 per GEMM tile, nb^3 per SYRK tile,
+ * nb^3 per TRSM tile, nb^3/3 per POTRF).  Reset clears all kinds. */
+int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on);
+int mpcr_ctx_reset_stats(mpcr_ctx* ctx);
+int mpcr_ctx_kernel_stats(const mpcr_ctx* ctx, int kind, double* h_total_ms, int64_t* h_launches,
+                          double* h_flops);
+
+/* ---- precision maps (host helpers) ----------------------------------------- */
+
+/* Banded map: tile (i, j), i >= j, with d = i - j gets precs[b] for the first
+ * band b with d <= band_dmax[b]; band_dmax[nbands-1] < 0 means "all the
+ * rest".  Writes nt*nt bytes to h_map_out (entries with i < j are set to 255).
+ * Errors: MPCR_ERR_ARG if the diagonal would not be FP64 or a distance has no
+ * band. */
+int mpcr_tilemap_banded(int64_t n, int64_t nb, const int* band_dmax, const int* precs,
+                        int nbands, uint8_t* h_map_out);
+
+/* Norm-guarded map: starts from the banded map and promotes each off-diagonal
+ * tile (i, j) to the lowest format p (in the order FP8 < FP16/BF16 < FP32 <
+ * FP64, never below the banded choice's precision rule) whose unit roundoff
+ * u_p satisfies u_p * max|Sigma_tile| <= guard.  h_tile_amax holds, row-major
+ * nt x nt, the largest magnitude of each lower tile (see
+ * mpcr_covariance_tile_amax).  Writes nt*nt bytes to h_map_out. */
+int mpcr_tilemap_guarded(int64_t n, int64_t nb, const uint8_t* h_banded_map,
+                         const double* h_tile_amax, double guard, uint8_t* h_map_out);
+
+/* ---- ordering and covariance ------------------------------------------------ */
+
+/* Morton (Z-order) permutation of n sites: each coordinate of d_locs (n x 2,
+ * column-major, values in [0,1)) is quantised to 16 bits
+ * (q = min(floor(65536 x), 65535)), bits interleaved with x in the even
+ * positions; d_perm_out (n int64, device) receives the stable sort order.
+ * Nearby sites get nearby indices, which is what a band map relies on. */
+int mpcr_morton_order(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d_perm_out);
+
+/* Dense FP64 covariance Sigma(theta) (n x n, column-major, ld >= n) from the
+ * sites d_locs (n x 2 column-major), both triangles written. */
+int mpcr_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* theta,
+                    double* d_A, int64_t lda);
+
+/* Largest |Sigma_ij| of every lower tile (i >= j) of the nb-tiled covariance,
+ * written to h_amax_out (HOST, nt*nt doubles, row-major; upper entries 0). */
+int mpcr_covariance_tile_amax(mpcr_ctx* ctx, int64_t n, int64_t nb, const double* d_locs,
+                              const mpcr_theta_t* theta, double* h_amax_out);
+
+/* ---- tile factorisation ----------------------------------------------------- */
+
+/* Mixed-precision right-looking tile Cholesky of the FP64 SPD matrix d_A
+ * (n x n, column-major, only the lower triangle is read).  Each lower tile is
+ * rounded once (round-to-nearest-even) to its map format; then for each step k:
+ * POTRF of the FP64 diagonal tile, TRSM of the panel tiles (computed in FP64,
+ * rounded once to each tile's format), SYRK into the diagonal tiles (FP64) and
+ * GEMM updates of the other trailing tiles computed in the OUTPUT tile's
+ * format (FP32 accumulation for 16- and 8-bit formats).
+ * *out receives a factor that owns its device tiles; *h_info receives 0 or
+ * the 1-based global column of the first non-positive pivot, in which case the
+ * call returns MPCR_ERR_NOT_SPD and *out is still valid (destroy it).
+ * FP8 tiles are not accepted here (MPCR_ERR_ARG). */
+int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda,
+                     const mpcr_tilemap_t* map, mpcr_factor** out, int64_t* h_info);
+
+/* Same factorisation with Sigma(theta) generated tile by tile from the sites
+ * (no dense FP64 matrix is formed). */
+int mpcr_potrf_tiled_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs,
+                                const mpcr_theta_t* theta, const mpcr_tilemap_t* map,
+                                mpcr_factor** out, int64_t* h_info);
+
+int mpcr_factor_destroy(mpcr_factor* f);
+
+/* log|Sigma| = 2 sum_i log L_ii over the first n diagonal entries, summed in
+ * FP64 in a fixed order.  *h_logdet receives the value. */
+int mpcr_factor_logdet(mpcr_ctx* ctx, const mpcr_factor* f, double* h_logdet);
+
+/* The factor widened to FP64 as a dense lower-triangular n x n matrix
+ * (column-major, ld >= n; strictly upper part set to 0).  For inspection. */
+int mpcr_factor_to_dense(mpcr_ctx* ctx, const mpcr_factor* f, double* d_L, int64_t ldl);
+
+/* Algorithmic factorisation flops split by compute format (host array of 5). */
+int mpcr_factor_flops(const mpcr_factor* f, double* h_flops5);
+
+/* ---- solves --------------------------------------------------------------- */
+
+/* Forward solve W = L^{-1} B (n x nrhs FP64, device), the first half of the
+ * paper's forwardsolve/backsolve pair; low-precision tiles are read widened. */
+int mpcr_trsm_forward(mpcr_ctx* ctx, const mpcr_factor* f, int64_t nrhs, const double* d_B,
+                      int64_t ldb, double* d_W, int64_t ldw);
+
+/* X = Sigma^{-1} B through the factor (forward then backward solve).  If
+ * d_A_fp64 is non-NULL (the FP64 matrix, n x n, both triangles) and opts is
+ * non-NULL with max_iter > 0, the solve is refined in FP64 against it (see
+ * mpcr_refine_opts_t).  diag may be NULL.  Returns MPCR_ERR_NOT_CONVERGED if
+ * refinement stopped at max_iter above tolerance (X holds the last iterate). */
+int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* f, int64_t nrhs, const double* d_B, int64_t ldb,
+               double* d_X, int64_t ldx, const double* d_A_fp64, int64_t lda,
+               const mpcr_refine_opts_t* opts, mpcr_diag_t* diag);
+
+/* Gaussian log-likelihood of nrhs observation vectors d_Z (n x nrhs, FP64,
+ * column-major, ld = n) at sites d_locs (n x 2, column-major):
+ *   l = -(n/2) log(2 pi) - (1/2) log|Sigma| - (1/2) z^T Sigma^{-1} z.
+ * Sites are taken in Morton order when `order` is 1 (l is invariant under a
+ * joint permutation of sites and observations).  map == NULL means all tiles
+ * FP64 with tile size nb_default (=256).  With an all-FP64 map and opts NULL
+ * the quadratic form is ||L^{-1} z||^2 (the paper's forwardsolve + SquareSum);
+ * otherwise the solve is refined in FP64 with the residual computed
+ * matrix-free from the sites, and quad = z^T x + x^T r.
+ * h_loglik (host, nrhs doubles) receives l per column; diag may be NULL.
+ * The covariance tiles and factor live in a workspace owned by ctx. */
+int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_Z,
+                      int64_t nrhs, const mpcr_theta_t* theta, const mpcr_tilemap_t* map,
+                      int order, const mpcr_refine_opts_t* opts, double* h_loglik,
+                      mpcr_diag_t* diag);
+
+/* ---- matrix product ----------------------------------------------------------- */
+
+/* Round an FP64 matrix (m x n, column-major, lds) once to format `prec`
+ * (round-to-nearest-even; FP8-E4M3FN saturating).  Element type of d_dst:
+ * double / float / uint16 bit patterns (FP16, BF16) / uint8 codes (FP8).
+ * For MPCR_FP8_E4M3 each 128 x 128 block (of the stored matrix) is first
+ * multiplied by 2^s with s = floor(log2(448 / max|block|)) (s = 0 for an
+ * all-zero block, clamped to [-128, 127]); s is written to d_scale_exp
+ * (int8, ceil(m/128) x ceil(n/128) column-major).  d_scale_exp must be NULL
+ * for the other formats. */
+int mpcr_convert(mpcr_ctx* ctx, mpcr_prec_t prec, int64_t m, int64_t n, const double* d_src,
+                 int64_t lds, void* d_dst, int64_t ldd, int8_t* d_scale_exp);
+
+/* C <- alpha op(A) op(B) + beta C (op = transpose if trans* != 0), A and B in
+ * format `prec` (as written by mpcr_convert, with their block scale exponents
+ * for FP8), C in c_prec (MPCR_FP64 for prec = FP64, MPCR_FP32 or MPCR_FP64
+ * otherwise).  FP64 accumulates in FP64, FP32 in FP32, FP16/BF16/FP8 in FP32;
+ * FP8 products are rescaled by 2^-(sA + sB) per 128-wide k block.
+ * m, n, k >= 0; ld* >= the stored row count. */
+int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m, int64_t n,
+              int64_t k, double alpha, const void* d_A, int64_t lda, const int8_t* d_scaleA_exp,
+              const void* d_B, int64_t ldb, const int8_t* d_scaleB_exp, double beta, void* d_C,
+              int64_t ldc, mpcr_prec_t c_prec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPCR_H */

@@ -129,11 +129,12 @@ def encode(x, f) -> np.ndarray:
 
 def pow2_scale_exponent(amax) -> np.ndarray:
     """Exponent s of the power-of-two scale 2^s that maps a block with largest
-    magnitude ``amax`` into FP8-E4M3FN range: s = floor(log2(448 / amax)),
-    and s = 0 for an all-zero block.  The exponent is stored as a signed byte,
-    so it is clamped to [-128, 127]."""
+    magnitude ``amax`` into FP8-E4M3FN range: the largest integer s with
+    amax * 2^s <= 448 (that is floor(log2(448 / amax)) evaluated exactly), and
+    s = 0 for an all-zero block.  The exponent is stored as a signed byte, so it
+    is clamped to [-128, 127]."""
     amax = np.asarray(amax, dtype=np.float64)
     pos = amax > 0
-    ratio = np.where(pos, 448.0 / np.where(pos, amax, 1.0), 1.0)
-    m, E = np.frexp(ratio)             # ratio = m 2^E, m in [0.5,1): floor(log2) = E - 1
-    return np.clip(np.where(pos, E - 1, 0), -128, 127).astype(np.int64)
+    m, E = np.frexp(np.where(pos, amax, 1.0))   # amax = m 2^E, m in [0.5, 1); 448 = 0.875 2^9
+    s = np.where(m <= 0.875, 9 - E, 8 - E)
+    return np.clip(np.where(pos, s, 0), -128, 127).astype(np.int64)

@@ -1,0 +1,1016 @@
+// C interface of the mpcr library: argument checking, device memory, and the
+// stream-ordered schedule of the tile kernels.  Every numerical step runs in
+// the HIP kernels of this library; the host only validates, allocates, queues
+// launches and reads back small result arrays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mpcr_internal.h"
+
+using namespace mpcr;
+
+struct mpcr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // workspace reused across mpcr_gauss_loglik calls of the same shape
+  mpcr_factor* ws_factor = nullptr;
+  std::vector<uint8_t> ws_map;
+  int64_t ws_n = -1, ws_nb = -1;
+  double* ws_locs = nullptr;      // n x 2 sorted sites
+  double* ws_vec = nullptr;       // vector workspace
+  int64_t ws_vec_bytes = 0;
+  hipEvent_t ev[6] = {};
+  // kernel timing (see mpcr_ctx_set_profiling)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending { hipEvent_t a, b; int kind; double flops; };
+  std::vector<Pending> pending;
+  double k_ms[7] = {0}, k_flops[7] = {0};
+  int64_t k_launches[7] = {0};
+};
+
+namespace {
+hipEvent_t take_event(mpcr_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+// Accumulates the elapsed times of recorded launches (the stream must have been synchronised).
+void drain_timing(mpcr_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->k_ms[p.kind] += ms;
+      ctx->k_launches[p.kind] += 1;
+      ctx->k_flops[p.kind] += p.flops;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+// Runs `launch` between two events when profiling is on.
+template <class F>
+hipError_t timed(mpcr_ctx* ctx, int kind, double flops, F&& launch) {
+  if (!ctx->profiling) return launch();
+  hipEvent_t a = take_event(ctx), b = take_event(ctx);
+  if (!a || !b) return launch();
+  hipError_t e = hipEventRecord(a, ctx->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  ctx->pending.push_back({a, b, kind, flops});
+  return e;
+}
+}  // namespace
+
+struct mpcr_factor {
+  int64_t n = 0, nb = 0, nt = 0, N = 0;
+  int device = 0;
+  std::vector<uint8_t> map;        // nt x nt, row-major, host
+  std::vector<uint8_t> fmt_packed; // per lower tile
+  std::vector<int64_t> off_packed; // byte offsets
+  uint8_t* d_base = nullptr;
+  int64_t* d_off = nullptr;
+  uint8_t* d_fmt = nullptr;
+  int* d_info = nullptr;
+  double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles
+  double* d_Linv = nullptr;        // 2 nt nb^2 doubles (inverses and their transposes)
+  bool linv_ready = false;
+  GemmTask* d_tasks = nullptr;
+  std::vector<int64_t> task_off;   // [(k * 5 + f)] offset into d_tasks
+  std::vector<int> task_cnt;
+  double flops[5] = {0, 0, 0, 0, 0};
+  int64_t info = 0;
+
+  TileView view() const {
+    TileView tv;
+    tv.base = d_base;
+    tv.off = d_off;
+    tv.fmt = d_fmt;
+    tv.nb = (int)nb;
+    tv.nt = (int)nt;
+    tv.n = (int)n;
+    tv.info = d_info;
+    return tv;
+  }
+};
+
+static const char* kVersion = "mpcr 0.1 gfx950";
+
+static int set_err(mpcr_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                      \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return set_err(ctx, e_ == hipErrorOutOfMemory ? MPCR_ERR_NOMEM : MPCR_ERR_DEVICE,        \
+                     "%s failed: %s", #expr, hipGetErrorString(e_));                            \
+  } while (0)
+
+#define CHECK_ARG(ctx, cond, ...)                                 \
+  do {                                                            \
+    if (!(cond)) return set_err(ctx, MPCR_ERR_ARG, __VA_ARGS__);  \
+  } while (0)
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+hipError_t dmalloc(T** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  return hipMalloc((void**)p, bytes);
+}
+
+void free_factor(mpcr_factor* f) {
+  if (!f) return;
+  DeviceGuard g(f->device);
+  (void)hipFree(f->d_base);
+  (void)hipFree(f->d_off);
+  (void)hipFree(f->d_fmt);
+  (void)hipFree(f->d_info);
+  (void)hipFree(f->d_trsm_ws);
+  (void)hipFree(f->d_Linv);
+  (void)hipFree(f->d_tasks);
+  delete f;
+}
+
+bool valid_prec(int p) { return p >= 0 && p <= 4; }
+
+// Checks a tile map and copies it (nt x nt) into out.
+int check_map(mpcr_ctx* ctx, int64_t n, const mpcr_tilemap_t* map, std::vector<uint8_t>& out, int64_t& nb,
+              bool allow_fp8) {
+  CHECK_ARG(ctx, map != nullptr, "map is NULL");
+  CHECK_ARG(ctx, map->n == n, "map->n (%lld) != n (%lld)", (long long)map->n, (long long)n);
+  nb = map->nb;
+  CHECK_ARG(ctx, nb >= 128 && nb % 128 == 0 && nb <= 4096, "nb must be a positive multiple of 128 (<= 4096)");
+  int64_t nt = (n + nb - 1) / nb;
+  CHECK_ARG(ctx, map->nt == nt, "map->nt must be ceil(n / nb) = %lld", (long long)nt);
+  CHECK_ARG(ctx, map->h_map != nullptr, "map->h_map is NULL");
+  out.assign(map->h_map, map->h_map + nt * nt);
+  for (int64_t i = 0; i < nt; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      int p = out[i * nt + j];
+      CHECK_ARG(ctx, valid_prec(p), "map(%lld,%lld) = %d is not a format", (long long)i, (long long)j, p);
+      if (i == j) CHECK_ARG(ctx, p == F64, "diagonal tile %lld must be FP64", (long long)i);
+      if (!allow_fp8) CHECK_ARG(ctx, p != F8, "FP8 tiles are not supported by the tile factorisation");
+    }
+  return MPCR_OK;
+}
+
+// Allocates a factor for the map and fills its task lists.
+int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>& map, mpcr_factor** out) {
+  DeviceGuard g(ctx->device);
+  auto* f = new mpcr_factor();
+  f->device = ctx->device;
+  f->n = n;
+  f->nb = nb;
+  f->nt = (n + nb - 1) / nb;
+  f->N = f->nt * nb;
+  f->map = map;
+  const int64_t nt = f->nt;
+  const int64_t ntiles = nt * (nt + 1) / 2;
+  f->fmt_packed.resize(ntiles);
+  f->off_packed.resize(ntiles);
+  int64_t off = 0;
+  for (int64_t i = 0; i < nt; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      int p = map[i * nt + j];
+      int64_t t = tri_index(i, j);
+      f->fmt_packed[t] = (uint8_t)p;
+      f->off_packed[t] = off;
+      off += ((nb * nb * fmt_bytes(p)) + 255) / 256 * 256;
+    }
+  // task lists: for each step k and compute format, the trailing tiles (i, j), j > k
+  std::vector<GemmTask> tasks;
+  f->task_off.assign(nt * 5, 0);
+  f->task_cnt.assign(nt * 5, 0);
+  for (int64_t k = 0; k < nt; ++k) {
+    f->flops[F64] += (double)nb * nb * nb / 3.0;
+    for (int64_t i = k + 1; i < nt; ++i) f->flops[F64] += 2.0 * (double)nb * nb * nb;  // TRSM + SYRK
+    for (int p = 0; p < 5; ++p) {
+      f->task_off[k * 5 + p] = (int64_t)tasks.size();
+      for (int64_t j = k + 1; j < nt; ++j)
+        for (int64_t i = j; i < nt; ++i)
+          if (map[i * nt + j] == p) {
+            tasks.push_back(GemmTask{(int)i, (int)j});
+            if (i != j) f->flops[p] += 2.0 * (double)nb * nb * nb;
+          }
+      f->task_cnt[k * 5 + p] = (int)((int64_t)tasks.size() - f->task_off[k * 5 + p]);
+    }
+  }
+  hipError_t e;
+  if ((e = dmalloc(&f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(&f->d_off, ntiles * 8)) != hipSuccess ||
+      (e = dmalloc(&f->d_fmt, ntiles)) != hipSuccess || (e = dmalloc(&f->d_info, sizeof(int))) != hipSuccess ||
+      (e = dmalloc(&f->d_trsm_ws, (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 8)) != hipSuccess ||
+      (e = dmalloc(&f->d_tasks, std::max<size_t>(tasks.size(), 1) * sizeof(GemmTask))) != hipSuccess) {
+    free_factor(f);
+    return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  hipStream_t s = ctx->stream;
+  if ((e = hipMemcpyAsync(f->d_off, f->off_packed.data(), ntiles * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(f->d_fmt, f->fmt_packed.data(), ntiles, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (tasks.size() &&
+       (e = hipMemcpyAsync(f->d_tasks, tasks.data(), tasks.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s)) !=
+           hipSuccess) ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    free_factor(f);
+    return set_err(ctx, MPCR_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+  }
+  *out = f;
+  return MPCR_OK;
+}
+
+// Queues the whole right-looking factorisation of an already filled tile store.
+int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
+  hipStream_t s = ctx->stream;
+  TileView tv = f->view();
+  f->linv_ready = false;
+  const double nb3 = (double)f->nb * f->nb * f->nb;
+  for (int64_t k = 0; k < f->nt; ++k) {
+    HIP_TRY(ctx, timed(ctx, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, s); }));
+    HIP_TRY(ctx, timed(ctx, 6, nb3 * (double)(f->nt - k - 1),
+                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, s); }));
+    static const int order[4] = {F64, F32, BF16, F16};
+    for (int p : order) {
+      int cnt = f->task_cnt[k * 5 + p];
+      if (!cnt) continue;
+      double fl = 2.0 * nb3 * cnt;
+      if (p == F64) fl -= nb3 * (double)(f->nt - k - 1);  // the SYRK tasks count nb^3 each
+      HIP_TRY(ctx, timed(ctx, p, fl, [&] {
+        return launch_tile_update(tv, (int)k, p, f->d_tasks + f->task_off[k * 5 + p], cnt, s);
+      }));
+    }
+  }
+  return MPCR_OK;
+}
+
+int read_info(mpcr_ctx* ctx, mpcr_factor* f, int64_t* h_info) {
+  int info = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&info, f->d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  drain_timing(ctx);
+  f->info = info;
+  if (h_info) *h_info = info;
+  if (info) return set_err(ctx, MPCR_ERR_NOT_SPD, "leading minor of order %d is not positive definite", info);
+  return MPCR_OK;
+}
+
+int ensure_linv(mpcr_ctx* ctx, mpcr_factor* f) {
+  if (f->linv_ready) return MPCR_OK;
+  if (!f->d_Linv) HIP_TRY(ctx, dmalloc(&f->d_Linv, (size_t)2 * f->nt * f->nb * f->nb * 8));
+  HIP_TRY(ctx, launch_trtri_diag(f->view(), f->d_Linv, ctx->stream));
+  f->linv_ready = true;
+  return MPCR_OK;
+}
+
+// Padded-order FP64 work blocks for the solves.
+struct SolveBufs {
+  int64_t N = 0, nrhs = 0;
+  double *B = nullptr, *X = nullptr, *W = nullptr, *R = nullptr, *V = nullptr;  // N x nrhs each
+  double *P = nullptr, *Q = nullptr, *Z = nullptr;
+  double *scal = nullptr;  // small per-column scalars
+  double *partial = nullptr;
+  int* active = nullptr;
+};
+
+int64_t solve_bytes(int64_t N, int64_t nrhs, int64_t n) {
+  int64_t blk = N * nrhs * 8;
+  int64_t nslab = (n + 1023) / 1024 + 1;
+  return 8 * blk + 16 * nrhs * 8 + nslab * nrhs * 5 * 8 + nrhs * 4 + 4096;
+}
+
+int carve(mpcr_ctx* ctx, int64_t N, int64_t nrhs, int64_t n, SolveBufs& b) {
+  int64_t need = solve_bytes(N, nrhs, n);
+  if (ctx->ws_vec_bytes < need) {
+    if (ctx->ws_vec) (void)hipFree(ctx->ws_vec);
+    ctx->ws_vec = nullptr;
+    ctx->ws_vec_bytes = 0;
+    HIP_TRY(ctx, dmalloc(&ctx->ws_vec, (size_t)need));
+    ctx->ws_vec_bytes = need;
+  }
+  char* p = (char*)ctx->ws_vec;
+  int64_t blk = N * nrhs * 8;
+  b.N = N;
+  b.nrhs = nrhs;
+  double** blocks[8] = {&b.B, &b.X, &b.W, &b.R, &b.V, &b.P, &b.Q, &b.Z};
+  for (auto bp : blocks) {
+    *bp = (double*)p;
+    p += blk;
+  }
+  b.scal = (double*)p;
+  p += 16 * nrhs * 8;
+  int64_t nslab = (n + 1023) / 1024 + 1;
+  b.partial = (double*)p;
+  p += nslab * nrhs * 5 * 8;
+  b.active = (int*)p;
+  HIP_TRY(ctx, launch_fill(ctx->ws_vec, 8 * N * nrhs, 0.0, ctx->stream));
+  return MPCR_OK;
+}
+
+// X = M^{-1} B with M = L L^T over the tiles; also leaves W = L^{-1} B.
+int tile_solve(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const double* Bsrc, double* Xdst, double* Wdst,
+               bool backward = true) {
+  hipStream_t s = ctx->stream;
+  TileView tv = f->view();
+  const int nrhs = (int)b.nrhs;
+  const int64_t ld = b.N;
+  // b.V is the working copy of both sweeps, so Bsrc may be any other block
+  HIP_TRY(ctx, launch_copy_cols((int)f->N, nrhs, Bsrc, ld, b.V, ld, s));
+  for (int64_t k = 0; k < f->nt; ++k) {
+    HIP_TRY(ctx, launch_fwd_diag(tv, f->d_Linv, (int)k, b.V, Wdst, ld, nrhs, s));
+    HIP_TRY(ctx, launch_fwd_update(tv, (int)k, b.V, Wdst, ld, nrhs, s));
+  }
+  if (!backward) return MPCR_OK;
+  HIP_TRY(ctx, launch_copy_cols((int)f->N, nrhs, Wdst, ld, b.V, ld, s));
+  for (int64_t k = f->nt - 1; k >= 0; --k) {
+    HIP_TRY(ctx, launch_bwd_diag(tv, f->d_Linv, (int)k, b.V, Xdst, ld, nrhs, s));
+    HIP_TRY(ctx, launch_bwd_update(tv, (int)k, b.V, Xdst, ld, nrhs, s));
+  }
+  return MPCR_OK;
+}
+
+// Sigma application for refinement: either matrix-free from sites or a dense FP64 matrix.
+struct SigmaOp {
+  const double* locs = nullptr;
+  mpcr_theta_t th{};
+  const double* A = nullptr;
+  int64_t lda = 0;
+  int n = 0;
+  hipError_t residual(const double* B, const double* X, double* R, int64_t ld, int nrhs, hipStream_t s) const {
+    return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s)
+             : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s);
+  }
+  hipError_t rowsum(double* out, hipStream_t s) const {
+    return A ? launch_rowsum_abs_dense(n, A, lda, out, s) : launch_rowsum_abs_cov(n, locs, th, out, s);
+  }
+};
+
+// Refined solve (PCG or IR) of Sigma X = B; B, X in b.B / b.X (padded N x nrhs).
+int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const mpcr_refine_opts_t& o,
+           mpcr_diag_t* diag, bool* converged_out) {
+  hipStream_t s = ctx->stream;
+  const int n = (int)f->n, nrhs = (int)b.nrhs;
+  const int64_t ld = b.N;
+  double* sig_inf = b.scal;                // [0]
+  double* rz = b.scal + nrhs;              // nrhs
+  double* pq = b.scal + 2 * nrhs;
+  double* alpha = b.scal + 3 * nrhs;
+  double* beta = b.scal + 4 * nrhs;
+  double* rzn = b.scal + 5 * nrhs;
+  double* stats = b.scal + 6 * nrhs;       // 2 nrhs
+  double* rowsum = b.Z;                    // temporary use before Z is needed
+  HIP_TRY(ctx, op.rowsum(rowsum, s));
+  HIP_TRY(ctx, launch_max_reduce(n, rowsum, b.partial, sig_inf, s));
+
+  std::vector<double> hst(2 * nrhs);
+  std::vector<int> act(nrhs, 1);
+  auto col_converged = [&](int c) { return hst[2 * c] <= o.tol; };
+  auto fetch_stats = [&](const double* R) -> int {
+    HIP_TRY(ctx, launch_col_stats(n, nrhs, R, b.X, b.B, ld, sig_inf, b.partial, stats, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hst.data(), stats, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return MPCR_OK;
+  };
+  auto push_active = [&]() -> int {
+    HIP_TRY(ctx, hipMemcpyAsync(b.active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+    return MPCR_OK;
+  };
+
+  int rc;
+  // x0 = M^{-1} b, r0 = b - Sigma x0
+  if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;
+  HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+  if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+  int nact = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    act[c] = col_converged(c) ? 0 : 1;
+    nact += act[c];
+  }
+  if ((rc = push_active()) != MPCR_OK) return rc;
+  int it = 0;
+  if (o.solver == 0) {
+    if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;  // z = M^{-1} r
+    HIP_TRY(ctx, launch_copy_cols((int)b.N, nrhs, b.Z, ld, b.P, ld, s));
+    HIP_TRY(ctx, launch_col_dot(n, nrhs, b.R, b.Z, ld, b.partial, rz, s));
+    while (nact > 0 && it < o.max_iter) {
+      ++it;
+      // q = Sigma p  (as -(0 - Sigma p) through the residual kernel with a zero right-hand side)
+      HIP_TRY(ctx, op.residual(nullptr, b.P, b.Q, ld, nrhs, s));  // Q = -Sigma P
+      HIP_TRY(ctx, launch_col_dot(n, nrhs, b.P, b.Q, ld, b.partial, pq, s));  // = -p^T Sigma p
+      HIP_TRY(ctx, launch_pcg_alpha(nrhs, rz, pq, b.active, alpha, s));      // = -alpha
+      HIP_TRY(ctx, launch_axpy_cols(n, nrhs, alpha, -1.0, b.P, b.X, ld, s)); // x += alpha p
+      if (o.recompute > 0 && it % o.recompute == 0) {
+        HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+      } else {
+        HIP_TRY(ctx, launch_axpy_cols(n, nrhs, alpha, -1.0, b.Q, b.R, ld, s)); // r -= alpha Sigma p
+      }
+      if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+      bool any = false;
+      for (int c = 0; c < nrhs; ++c) any |= act[c] && col_converged(c);
+      if (any) {  // confirm with the true residual
+        HIP_TRY(ctx, op.residual(b.B, b.X, b.W, ld, nrhs, s));
+        if ((rc = fetch_stats(b.W)) != MPCR_OK) return rc;
+        HIP_TRY(ctx, launch_copy_cols(n, nrhs, b.W, ld, b.R, ld, s));
+        for (int c = 0; c < nrhs; ++c)
+          if (act[c] && col_converged(c)) {
+            act[c] = 0;
+            --nact;
+          }
+        if ((rc = push_active()) != MPCR_OK) return rc;
+      }
+      if (nact == 0 || it >= o.max_iter) break;
+      if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;
+      HIP_TRY(ctx, launch_col_dot(n, nrhs, b.R, b.Z, ld, b.partial, rzn, s));
+      HIP_TRY(ctx, launch_pcg_beta(nrhs, rzn, rz, b.active, beta, s));
+      HIP_TRY(ctx, launch_xpby_cols(n, nrhs, b.Z, beta, b.P, ld, s));
+    }
+  } else {
+    while (nact > 0 && it < o.max_iter) {
+      ++it;
+      if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;
+      // x += d for active columns (alpha = active ? 1 : 0)
+      std::vector<double> ones(nrhs);
+      for (int c = 0; c < nrhs; ++c) ones[c] = act[c] ? 1.0 : 0.0;
+      HIP_TRY(ctx, hipMemcpyAsync(alpha, ones.data(), nrhs * 8, hipMemcpyHostToDevice, s));
+      HIP_TRY(ctx, launch_axpy_cols(n, nrhs, alpha, 1.0, b.Z, b.X, ld, s));
+      HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+      if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+      for (int c = 0; c < nrhs; ++c)
+        if (act[c] && col_converged(c)) {
+          act[c] = 0;
+          --nact;
+        }
+    }
+  }
+  // final true residual and statistics
+  HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+  if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+  bool conv = true;
+  double eta = 0, rel = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    conv &= col_converged(c);
+    eta = std::max(eta, hst[2 * c]);
+    rel = std::max(rel, hst[2 * c + 1]);
+  }
+  if (diag) {
+    diag->iters = it;
+    diag->converged = conv ? 1 : 0;
+    diag->eta = eta;
+    diag->rel_resid2 = rel;
+  }
+  *converged_out = conv;
+  return MPCR_OK;
+}
+
+float ev_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
+  return ms;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported entry points
+// ===========================================================================
+extern "C" {
+
+const char* mpcr_version(void) { return kVersion; }
+
+int mpcr_ctx_create(int device, void* hip_stream, mpcr_ctx** out) {
+  if (!out) return MPCR_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return MPCR_ERR_DEVICE;
+  if (device < 0 || device >= ndev) return MPCR_ERR_ARG;
+  auto* c = new mpcr_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  DeviceGuard g(device);
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return MPCR_ERR_DEVICE;
+    }
+  *out = c;
+  return MPCR_OK;
+}
+
+int mpcr_ctx_destroy(mpcr_ctx* ctx) {
+  if (!ctx) return MPCR_ERR_ARG;
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    free_factor(ctx->ws_factor);
+    (void)hipFree(ctx->ws_locs);
+    (void)hipFree(ctx->ws_vec);
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    drain_timing(ctx);
+    for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+  return MPCR_OK;
+}
+
+const char* mpcr_last_error(const mpcr_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on) {
+  if (!ctx) return MPCR_ERR_ARG;
+  ctx->profiling = on != 0;
+  return MPCR_OK;
+}
+
+int mpcr_ctx_reset_stats(mpcr_ctx* ctx) {
+  if (!ctx) return MPCR_ERR_ARG;
+  for (int k = 0; k < 7; ++k) {
+    ctx->k_ms[k] = 0;
+    ctx->k_flops[k] = 0;
+    ctx->k_launches[k] = 0;
+  }
+  return MPCR_OK;
+}
+
+int mpcr_ctx_kernel_stats(const mpcr_ctx* ctx, int kind, double* h_total_ms, int64_t* h_launches, double* h_flops) {
+  if (!ctx || kind < 0 || kind > 6) return MPCR_ERR_ARG;
+  if (h_total_ms) *h_total_ms = ctx->k_ms[kind];
+  if (h_launches) *h_launches = ctx->k_launches[kind];
+  if (h_flops) *h_flops = ctx->k_flops[kind];
+  return MPCR_OK;
+}
+
+int mpcr_tilemap_banded(int64_t n, int64_t nb, const int* band_dmax, const int* precs, int nbands,
+                        uint8_t* h_map_out) {
+  if (n < 0 || nb <= 0 || !band_dmax || !precs || nbands <= 0 || !h_map_out) return MPCR_ERR_ARG;
+  int64_t nt = (n + nb - 1) / nb;
+  for (int b = 0; b < nbands; ++b)
+    if (!valid_prec(precs[b])) return MPCR_ERR_ARG;
+  for (int64_t i = 0; i < nt; ++i)
+    for (int64_t j = 0; j < nt; ++j) {
+      if (j > i) {
+        h_map_out[i * nt + j] = 255;
+        continue;
+      }
+      int64_t d = i - j;
+      int p = -1;
+      for (int b = 0; b < nbands; ++b)
+        if (band_dmax[b] < 0 || d <= band_dmax[b]) {
+          p = precs[b];
+          break;
+        }
+      if (p < 0) return MPCR_ERR_ARG;
+      if (d == 0 && p != F64) return MPCR_ERR_ARG;
+      h_map_out[i * nt + j] = (uint8_t)p;
+    }
+  return MPCR_OK;
+}
+
+int mpcr_tilemap_guarded(int64_t n, int64_t nb, const uint8_t* h_banded_map, const double* h_tile_amax,
+                         double guard, uint8_t* h_map_out) {
+  if (n < 0 || nb <= 0 || !h_banded_map || !h_tile_amax || !h_map_out || !(guard > 0)) return MPCR_ERR_ARG;
+  int64_t nt = (n + nb - 1) / nb;
+  // precision rank: FP8 0, FP16/BF16 1, FP32 2, FP64 3
+  auto rank = [](int p) { return p == F64 ? 3 : p == F32 ? 2 : p == F8 ? 0 : 1; };
+  for (int64_t i = 0; i < nt; ++i)
+    for (int64_t j = 0; j < nt; ++j) {
+      int64_t t = i * nt + j;
+      if (j > i) {
+        h_map_out[t] = 255;
+        continue;
+      }
+      int p = h_banded_map[t];
+      if (!valid_prec(p)) return MPCR_ERR_ARG;
+      if (i == j && p != F64) return MPCR_ERR_ARG;
+      // promote until u_p * amax <= guard
+      while (p != F64 && fmt_unit_roundoff(p) * h_tile_amax[t] > guard) {
+        int r = rank(p);
+        p = r == 0 ? F16 : (r == 1 ? F32 : F64);
+        if (rank(p) == 1 && h_banded_map[t] == BF16) p = BF16;  // stay in the map's 16-bit flavour
+        if (p == BF16 && fmt_unit_roundoff(BF16) * h_tile_amax[t] > guard) p = F32;
+      }
+      h_map_out[t] = (uint8_t)p;
+    }
+  return MPCR_OK;
+}
+
+int mpcr_morton_order(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d_perm_out) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, n >= 0 && n < (1ll << 31), "n out of range");
+  CHECK_ARG(ctx, n == 0 || (d_locs && d_perm_out), "NULL pointer");
+  if (n == 0) return MPCR_OK;
+  DeviceGuard g(ctx->device);
+  int npow2 = 1;
+  while (npow2 < n) npow2 <<= 1;
+  uint64_t* keys = nullptr;
+  HIP_TRY(ctx, dmalloc(&keys, (size_t)npow2 * 8));
+  hipStream_t s = ctx->stream;
+  hipError_t e = launch_morton_codes((int)n, d_locs, keys, npow2, s);
+  if (e == hipSuccess) e = launch_bitonic_sort(keys, npow2, s);
+  if (e == hipSuccess) e = launch_keys_to_perm((int)n, keys, d_perm_out, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(keys);
+  HIP_TRY(ctx, e);
+  return MPCR_OK;
+}
+
+static int check_theta(mpcr_ctx* ctx, const mpcr_theta_t* th) {
+  CHECK_ARG(ctx, th != nullptr, "theta is NULL");
+  CHECK_ARG(ctx, th->nu == 0.5 || th->nu == 1.5 || th->nu == 2.5, "nu must be 0.5, 1.5 or 2.5");
+  CHECK_ARG(ctx, th->sigma2 > 0 && th->range > 0 && th->nugget >= 0 && std::isfinite(th->sigma2) &&
+                     std::isfinite(th->range) && std::isfinite(th->nugget),
+            "need sigma2 > 0, range > 0, nugget >= 0");
+  return MPCR_OK;
+}
+
+int mpcr_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* theta, double* d_A,
+                    int64_t lda) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  int rc = check_theta(ctx, theta);
+  if (rc) return rc;
+  CHECK_ARG(ctx, n >= 0 && n < (1ll << 31) && lda >= std::max<int64_t>(n, 1), "bad n / lda");
+  CHECK_ARG(ctx, n == 0 || (d_locs && d_A), "NULL pointer");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(ctx, launch_covariance_dense((int)n, d_locs, *theta, d_A, lda, ctx->stream));
+  return MPCR_OK;
+}
+
+int mpcr_covariance_tile_amax(mpcr_ctx* ctx, int64_t n, int64_t nb, const double* d_locs, const mpcr_theta_t* theta,
+                              double* h_amax_out) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  int rc = check_theta(ctx, theta);
+  if (rc) return rc;
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && nb > 0 && d_locs && h_amax_out, "bad arguments");
+  DeviceGuard g(ctx->device);
+  int64_t nt = (n + nb - 1) / nb;
+  double* d = nullptr;
+  HIP_TRY(ctx, dmalloc(&d, (size_t)nt * nt * 8));
+  hipError_t e = hipMemsetAsync(d, 0, nt * nt * 8, ctx->stream);
+  if (e == hipSuccess) e = launch_covariance_tile_amax((int)n, (int)nb, d_locs, *theta, d, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_amax_out, d, nt * nt * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(d);
+  HIP_TRY(ctx, e);
+  return MPCR_OK;
+}
+
+int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda, const mpcr_tilemap_t* map,
+                     mpcr_factor** out, int64_t* h_info) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, out != nullptr, "out is NULL");
+  *out = nullptr;
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && lda >= n && d_A, "bad n / lda / A");
+  std::vector<uint8_t> m;
+  int64_t nb;
+  int rc = check_map(ctx, n, map, m, nb, false);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  mpcr_factor* f = nullptr;
+  if ((rc = make_factor(ctx, n, nb, m, &f)) != MPCR_OK) return rc;
+  *out = f;
+  HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), ctx->stream));
+  HIP_TRY(ctx, launch_tiles_from_dense(f->view(), d_A, lda, ctx->stream));
+  if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
+  return read_info(ctx, f, h_info);
+}
+
+int mpcr_potrf_tiled_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* theta,
+                                const mpcr_tilemap_t* map, mpcr_factor** out, int64_t* h_info) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, out != nullptr, "out is NULL");
+  *out = nullptr;
+  int rc = check_theta(ctx, theta);
+  if (rc) return rc;
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs, "bad n / locs");
+  std::vector<uint8_t> m;
+  int64_t nb;
+  if ((rc = check_map(ctx, n, map, m, nb, false)) != MPCR_OK) return rc;
+  DeviceGuard g(ctx->device);
+  mpcr_factor* f = nullptr;
+  if ((rc = make_factor(ctx, n, nb, m, &f)) != MPCR_OK) return rc;
+  *out = f;
+  HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), ctx->stream));
+  HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), d_locs, *theta, ctx->stream));
+  if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
+  return read_info(ctx, f, h_info);
+}
+
+int mpcr_factor_destroy(mpcr_factor* f) {
+  if (!f) return MPCR_ERR_ARG;
+  free_factor(f);
+  return MPCR_OK;
+}
+
+int mpcr_factor_logdet(mpcr_ctx* ctx, const mpcr_factor* fc, double* h_logdet) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, fc && h_logdet, "NULL argument");
+  CHECK_ARG(ctx, fc->info == 0, "factor is not positive definite (info %lld)", (long long)fc->info);
+  DeviceGuard g(ctx->device);
+  double* d = nullptr;
+  HIP_TRY(ctx, dmalloc(&d, 8));
+  hipError_t e = launch_logdet(fc->view(), d, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_logdet, d, 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(d);
+  HIP_TRY(ctx, e);
+  return MPCR_OK;
+}
+
+int mpcr_factor_to_dense(mpcr_ctx* ctx, const mpcr_factor* fc, double* d_L, int64_t ldl) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, fc && d_L && ldl >= fc->n, "bad arguments");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(ctx, launch_tiles_to_dense(fc->view(), d_L, ldl, ctx->stream));
+  return MPCR_OK;
+}
+
+int mpcr_factor_flops(const mpcr_factor* f, double* h_flops5) {
+  if (!f || !h_flops5) return MPCR_ERR_ARG;
+  for (int p = 0; p < 5; ++p) h_flops5[p] = f->flops[p];
+  return MPCR_OK;
+}
+
+int mpcr_trsm_forward(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double* d_B, int64_t ldb,
+                      double* d_W, int64_t ldw) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, fc != nullptr, "factor is NULL");
+  CHECK_ARG(ctx, fc->info == 0, "factor is not positive definite");
+  CHECK_ARG(ctx, nrhs >= 0 && ldb >= fc->n && ldw >= fc->n, "bad nrhs / ld");
+  if (nrhs == 0) return MPCR_OK;
+  CHECK_ARG(ctx, d_B && d_W, "NULL pointer");
+  auto* f = const_cast<mpcr_factor*>(fc);
+  DeviceGuard g(ctx->device);
+  int rc = ensure_linv(ctx, f);
+  if (rc) return rc;
+  SolveBufs b;
+  if ((rc = carve(ctx, f->N, nrhs, f->n, b)) != MPCR_OK) return rc;
+  HIP_TRY(ctx, launch_copy_cols((int)f->n, (int)nrhs, d_B, ldb, b.B, b.N, ctx->stream));
+  if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W, false)) != MPCR_OK) return rc;
+  HIP_TRY(ctx, launch_copy_cols((int)f->n, (int)nrhs, b.W, b.N, d_W, ldw, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPCR_OK;
+}
+
+int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double* d_B, int64_t ldb, double* d_X,
+               int64_t ldx, const double* d_A_fp64, int64_t lda, const mpcr_refine_opts_t* opts, mpcr_diag_t* diag) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, fc != nullptr, "factor is NULL");
+  CHECK_ARG(ctx, fc->info == 0, "factor is not positive definite");
+  CHECK_ARG(ctx, nrhs >= 0 && ldb >= fc->n && ldx >= fc->n, "bad nrhs / ld");
+  if (nrhs == 0) return MPCR_OK;
+  CHECK_ARG(ctx, d_B && d_X, "NULL pointer");
+  const bool do_ref = d_A_fp64 && opts && opts->max_iter > 0;
+  if (do_ref) {
+    CHECK_ARG(ctx, lda >= fc->n, "lda < n");
+    CHECK_ARG(ctx, opts->tol > 0 && opts->solver >= 0 && opts->solver <= 1 && opts->recompute >= 0, "bad opts");
+  }
+  auto* f = const_cast<mpcr_factor*>(fc);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  int rc = ensure_linv(ctx, f);
+  if (rc) return rc;
+  SolveBufs b;
+  if ((rc = carve(ctx, f->N, nrhs, f->n, b)) != MPCR_OK) return rc;
+  HIP_TRY(ctx, launch_copy_cols((int)f->n, (int)nrhs, d_B, ldb, b.B, b.N, s));
+  bool conv = true;
+  if (do_ref) {
+    SigmaOp op;
+    op.A = d_A_fp64;
+    op.lda = lda;
+    op.n = (int)f->n;
+    if ((rc = refine(ctx, f, b, op, *opts, diag, &conv)) != MPCR_OK) return rc;
+  } else {
+    if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;
+    if (diag) diag->iters = 0;
+  }
+  HIP_TRY(ctx, launch_copy_cols((int)f->n, (int)nrhs, b.X, b.N, d_X, ldx, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (diag) diag->info = 0;
+  if (!conv) return set_err(ctx, MPCR_ERR_NOT_CONVERGED, "refinement did not reach the tolerance");
+  return MPCR_OK;
+}
+
+int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_Z, int64_t nrhs,
+                      const mpcr_theta_t* theta, const mpcr_tilemap_t* map, int order, const mpcr_refine_opts_t* opts,
+                      double* h_loglik, mpcr_diag_t* diag) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  int rc = check_theta(ctx, theta);
+  if (rc) return rc;
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && nrhs >= 1 && nrhs <= 4096, "need n > 0 and 1 <= nrhs <= 4096");
+  CHECK_ARG(ctx, d_locs && d_Z && h_loglik, "NULL pointer");
+  std::vector<uint8_t> m;
+  int64_t nb = 256;
+  if (map) {
+    if ((rc = check_map(ctx, n, map, m, nb, false)) != MPCR_OK) return rc;
+  } else {
+    int64_t nt = (n + nb - 1) / nb;
+    m.assign(nt * nt, 255);
+    for (int64_t i = 0; i < nt; ++i)
+      for (int64_t j = 0; j <= i; ++j) m[i * nt + j] = F64;
+  }
+  bool all64 = true;
+  {
+    int64_t nt = (n + nb - 1) / nb;
+    for (int64_t i = 0; i < nt; ++i)
+      for (int64_t j = 0; j <= i; ++j) all64 &= (m[i * nt + j] == F64);
+  }
+  if (opts) CHECK_ARG(ctx, opts->tol > 0 && opts->solver >= 0 && opts->solver <= 1 && opts->recompute >= 0 &&
+                               opts->max_iter >= 0,
+                      "bad refinement options");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+
+  // workspace: factor of this shape and map, sorted sites
+  if (!ctx->ws_factor || ctx->ws_n != n || ctx->ws_nb != nb || ctx->ws_map != m) {
+    free_factor(ctx->ws_factor);
+    ctx->ws_factor = nullptr;
+    (void)hipFree(ctx->ws_locs);
+    ctx->ws_locs = nullptr;
+    ctx->ws_n = -1;
+    if ((rc = make_factor(ctx, n, nb, m, &ctx->ws_factor)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, dmalloc(&ctx->ws_locs, (size_t)n * 2 * 8 + (size_t)n * 8));
+    ctx->ws_n = n;
+    ctx->ws_nb = nb;
+    ctx->ws_map = m;
+  }
+  mpcr_factor* f = ctx->ws_factor;
+  SolveBufs b;
+  if ((rc = carve(ctx, f->N, nrhs, n, b)) != MPCR_OK) return rc;
+  double* locs = ctx->ws_locs;
+  int64_t* perm = (int64_t*)(ctx->ws_locs + 2 * n);
+
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
+  if (order) {
+    int npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
+    // keys live in the X block (N * nrhs * 8 >= npow2 * 8 is not guaranteed): use P..Z blocks if needed
+    uint64_t* keys = nullptr;
+    bool own = false;
+    if ((int64_t)npow2 * 8 <= 3 * f->N * nrhs * 8) {
+      keys = (uint64_t*)b.P;
+    } else {
+      HIP_TRY(ctx, dmalloc(&keys, (size_t)npow2 * 8));
+      own = true;
+    }
+    hipError_t e = launch_morton_codes((int)n, d_locs, keys, npow2, s);
+    if (e == hipSuccess) e = launch_bitonic_sort(keys, npow2, s);
+    if (e == hipSuccess) e = launch_keys_to_perm((int)n, keys, perm, s);
+    if (e == hipSuccess) e = launch_gather_rows((int)n, 2, d_locs, n, perm, locs, n, s);
+    if (e == hipSuccess) e = launch_gather_rows((int)n, (int)nrhs, d_Z, n, perm, b.B, b.N, s);
+    if (own) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(keys);
+    }
+    HIP_TRY(ctx, e);
+    HIP_TRY(ctx, launch_fill(b.P, 3 * b.N * nrhs, 0.0, s));
+  } else {
+    HIP_TRY(ctx, launch_copy_cols((int)n, 2, d_locs, n, locs, n, s));
+    HIP_TRY(ctx, launch_copy_cols((int)n, (int)nrhs, d_Z, n, b.B, b.N, s));
+  }
+  HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), s));
+  HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
+  if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+  int64_t info = 0;
+  rc = read_info(ctx, f, &info);
+  if (diag) {
+    memset(diag, 0, sizeof *diag);
+    diag->info = info;
+    for (int p = 0; p < 5; ++p) diag->flops_by_prec[p] = f->flops[p];
+  }
+  if (rc) return rc;
+
+  double* d_logdet = b.scal + 8 * nrhs;
+  double* d_quad = b.scal + 9 * nrhs;
+  double* d_ll = b.scal + 10 * nrhs;
+  HIP_TRY(ctx, launch_logdet(f->view(), d_logdet, s));
+  if ((rc = ensure_linv(ctx, f)) != MPCR_OK) return rc;
+  bool conv = true;
+  const bool refine_on = opts && opts->max_iter > 0;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
+  if (all64 && !refine_on) {
+    // the paper's path: w = L^{-1} z, quad = ||w||^2, and x = L^{-T} w
+    if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, launch_col_dot((int)n, (int)nrhs, b.W, b.W, b.N, b.partial, d_quad, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[4], s));
+    if (diag) {  // report the backward error of the direct solve
+      SigmaOp op;
+      op.locs = locs;
+      op.th = *theta;
+      op.n = (int)n;
+      double* sig_inf = b.scal;
+      double* stats = b.scal + 6 * nrhs;
+      HIP_TRY(ctx, op.rowsum(b.Z, s));
+      HIP_TRY(ctx, launch_max_reduce((int)n, b.Z, b.partial, sig_inf, s));
+      HIP_TRY(ctx, op.residual(b.B, b.X, b.R, b.N, (int)nrhs, s));
+      HIP_TRY(ctx, launch_col_stats((int)n, (int)nrhs, b.R, b.X, b.B, b.N, sig_inf, b.partial, stats, s));
+      std::vector<double> hst(2 * nrhs);
+      HIP_TRY(ctx, hipMemcpyAsync(hst.data(), stats, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      for (int64_t c = 0; c < nrhs; ++c) {
+        diag->eta = std::max(diag->eta, hst[2 * c]);
+        diag->rel_resid2 = std::max(diag->rel_resid2, hst[2 * c + 1]);
+      }
+      diag->converged = 1;
+    }
+  } else {
+    mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0};
+    SigmaOp op;
+    op.locs = locs;
+    op.th = *theta;
+    op.n = (int)n;
+    if (o.max_iter > 0) {
+      if ((rc = refine(ctx, f, b, op, o, diag, &conv)) != MPCR_OK) return rc;
+    } else {
+      if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;
+      HIP_TRY(ctx, op.residual(b.B, b.X, b.R, b.N, (int)nrhs, s));
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[4], s));
+    HIP_TRY(ctx, launch_quad_refined((int)n, (int)nrhs, b.B, b.X, b.R, b.N, b.partial, d_quad, s));
+  }
+  HIP_TRY(ctx, launch_loglik((int)n, (int)nrhs, d_logdet, d_quad, d_ll, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[5], s));
+  HIP_TRY(ctx, hipMemcpyAsync(h_loglik, d_ll, nrhs * 8, hipMemcpyDeviceToHost, s));
+  double host_ld = 0, host_q0 = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&host_ld, d_logdet, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(&host_q0, d_quad, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (diag) {
+    diag->logdet = host_ld;
+    diag->quad0 = host_q0;
+    diag->t_gen_ms = ev_ms(ctx->ev[0], ctx->ev[1]);
+    diag->t_factor_ms = ev_ms(ctx->ev[1], ctx->ev[2]);
+    diag->t_solve_ms = ev_ms(ctx->ev[3], ctx->ev[4]);
+    diag->t_refine_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
+  }
+  if (!conv) return set_err(ctx, MPCR_ERR_NOT_CONVERGED, "refinement did not reach the tolerance");
+  return MPCR_OK;
+}
+
+int mpcr_convert(mpcr_ctx* ctx, mpcr_prec_t prec, int64_t m, int64_t n, const double* d_src, int64_t lds, void* d_dst,
+                 int64_t ldd, int8_t* d_scale_exp) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, valid_prec(prec), "bad format");
+  CHECK_ARG(ctx, m >= 0 && n >= 0 && lds >= std::max<int64_t>(m, 1) && ldd >= std::max<int64_t>(m, 1), "bad shape");
+  CHECK_ARG(ctx, (m == 0 || n == 0) || (d_src && d_dst), "NULL pointer");
+  CHECK_ARG(ctx, ((int)prec == F8) == (d_scale_exp != nullptr), "scale exponents go with (and only with) FP8");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(ctx, launch_convert(prec, m, n, d_src, lds, d_dst, ldd, d_scale_exp, ctx->stream));
+  return MPCR_OK;
+}
+
+int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha,
+              const void* d_A, int64_t lda, const int8_t* d_scaleA_exp, const void* d_B, int64_t ldb,
+              const int8_t* d_scaleB_exp, double beta, void* d_C, int64_t ldc, mpcr_prec_t c_prec) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  const int p = (int)prec, cp = (int)c_prec;
+  CHECK_ARG(ctx, valid_prec(p) && (cp == F64 || cp == F32), "bad formats");
+  CHECK_ARG(ctx, !(p == F64 && cp != F64), "FP64 products are written in FP64");
+  CHECK_ARG(ctx, m >= 0 && n >= 0 && k >= 0, "negative size");
+  const int64_t arows = transA ? k : m, brows = transB ? n : k;
+  CHECK_ARG(ctx, lda >= std::max<int64_t>(arows, 1) && ldb >= std::max<int64_t>(brows, 1) &&
+                     ldc >= std::max<int64_t>(m, 1),
+            "leading dimension too small");
+  if (m == 0 || n == 0) return MPCR_OK;
+  CHECK_ARG(ctx, d_C && (k == 0 || (d_A && d_B)), "NULL pointer");
+  CHECK_ARG(ctx, (p == F8) == (d_scaleA_exp != nullptr && d_scaleB_exp != nullptr) || k == 0,
+            "FP8 operands need their scale exponents (and only FP8 takes them)");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(ctx, launch_gemm(prec, transA, transB, m, n, k, alpha, d_A, lda, d_scaleA_exp, d_B, ldb, d_scaleB_exp, beta,
+                           d_C, ldc, c_prec, ctx->stream));
+  return MPCR_OK;
+}
+
+}  // extern "C"

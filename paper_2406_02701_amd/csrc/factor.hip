@@ -1,0 +1,542 @@
+// Tile Cholesky kernels (gfx950).
+//
+// Right-looking tile Cholesky over nb x nb tiles held in per-tile formats
+// (the tiled multi-precision algorithm named in the paper's "Discussion and
+// Future Work" section; the factor feeds the log-determinant and the solves
+// of the MLE section):
+//   POTRF  L_kk = chol(A_kk)                          FP64, one workgroup
+//   TRSM   L_ik = A_ik L_kk^{-T}                      FP64 compute, rounded once to p(i,k)
+//   SYRK   A_jj -= L_jk L_jk^T                        FP64 MFMA
+//   GEMM   A_ij -= L_ik L_jk^T (i > j)                MFMA in the format of tile (i,j)
+// Every kernel first checks the device info word and does nothing once a
+// pivot has failed, so a whole factorisation can be queued without host syncs.
+#include "mpcr_internal.h"
+
+namespace mpcr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// MFMA 16x16 lane layouts on gfx950 (checked with an in-bounds probe):
+//   operands (f64 16x16x4, f32 16x16x4): lane l holds A[l%16][l/16], B[l/16][l%16]
+//   operands (bf16/f16 16x16x32): lane l holds A[l%16][8(l/16) .. 8(l/16)+7], B likewise
+//   result f32: lane l, register r -> D[4(l/16) + r][l%16]
+//   result f64: lane l, register r -> D[l/16 + 4r][l%16]
+
+// ---------------------------------------------------------------------------
+// operand conversion on load (A7a: the update runs in the output tile's format)
+// ---------------------------------------------------------------------------
+template <int CF> struct CTraits;
+template <> struct CTraits<F64> { using T = double; };
+template <> struct CTraits<F32> { using T = float; };
+template <> struct CTraits<BF16> { using T = uint16_t; };
+template <> struct CTraits<F16> { using T = uint16_t; };
+
+template <int CF>
+__device__ __forceinline__ typename CTraits<CF>::T load_as(const void* p, int f, int64_t idx) {
+  if constexpr (CF == F64) {
+    return load_wide(p, f, idx);
+  } else if constexpr (CF == F32) {
+    if (f == F32) return ((const float*)p)[idx];
+    return to_f32(load_wide(p, f, idx));
+  } else if constexpr (CF == BF16) {
+    if (f == BF16) return ((const uint16_t*)p)[idx];
+    if (f == F32) return f32_to_bf16_rne(((const float*)p)[idx]);
+    return to_bf16(load_wide(p, f, idx));
+  } else {
+    if (f == F16) return ((const uint16_t*)p)[idx];
+    if (f == F32) return __builtin_bit_cast(uint16_t, (_Float16)((const float*)p)[idx]);
+    return to_f16(load_wide(p, f, idx));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched tile update  C(i,j) -= A(i,k) B(j,k)^T, one 128 x 128 block of C per
+// workgroup (4 waves, 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles of 16 x 16)
+// ---------------------------------------------------------------------------
+constexpr int UBM = 128;
+
+// FP64 / FP32: operands staged k-major in LDS ([k][m]); fragments are
+// contiguous across lanes.
+template <int CF>
+__global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
+  using T = typename CTraits<CF>::T;
+  constexpr int BK = (CF == F64) ? 16 : 32;
+  constexpr int PAD = (CF == F64) ? 2 : 4;
+  constexpr int G = BK / 8;  // 4-row groups per thread per operand
+  __shared__ __attribute__((aligned(16))) T As[BK][UBM + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[BK][UBM + PAD];
+
+  const int nb = tv.nb;
+  const int sub = nb / UBM;
+  const int task = blockIdx.x / (sub * sub);
+  const int blk = blockIdx.x % (sub * sub);
+  const int bm = blk % sub, bn = blk / sub;
+  const GemmTask t = tasks[task];
+  if (t.i == t.j && bn > bm) return;
+  if (*tv.info) return;
+
+  const void* Ap = tv.tile(t.i, k);
+  const void* Bp = tv.tile(t.j, k);
+  const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lr = (tid & 31) * 4;  // loader rows lr .. lr+3
+  const int lc = tid >> 5;        // loader column (+ 8 g)
+  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
+
+  T ra[G][4], rb[G][4];
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      int64_t col = kk + lc + 8 * g;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        ra[g][r] = load_as<CF>(Ap, fa, col * nb + arow0 + lr + r);
+        rb[g][r] = load_as<CF>(Bp, fb, col * nb + brow0 + lr + r);
+      }
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        As[lc + 8 * g][lr + r] = ra[g][r];
+        Bs[lc + 8 * g][lr + r] = rb[g][r];
+      }
+  };
+
+  using Acc = typename std::conditional<CF == F64, d4, f4>::type;
+  Acc acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  gload(0);
+  for (int kk = 0; kk < nb; kk += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (kk + BK < nb) gload(kk + BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[k4 + (lane >> 4)][wm * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[k4 + (lane >> 4)][wn * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (CF == F64)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+
+  void* Cp = tv.tile(t.i, t.j);
+  const int fc = tv.tfmt(t.i, t.j);
+  const bool diag = (t.i == t.j);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = (CF == F64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
+        int64_t R = arow0 + wm * 64 + a * 16 + row;
+        int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
+        if (diag && C > R) continue;
+        int64_t idx = C * nb + R;
+        double c = load_wide(Cp, fc, idx) - (double)acc[a][b][r];
+        store_round(Cp, fc, idx, c);
+      }
+}
+
+// BF16 / FP16: operands staged m-major in LDS ([m][k]) so that each lane reads
+// its 8 consecutive k values with one 16-byte load.
+template <int CF>
+__global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const GemmTask* tasks) {
+  constexpr int BK = 64;
+  constexpr int LDK = BK + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t As[UBM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[UBM][LDK];
+
+  const int nb = tv.nb;
+  const int sub = nb / UBM;
+  const int task = blockIdx.x / (sub * sub);
+  const int blk = blockIdx.x % (sub * sub);
+  const int bm = blk % sub, bn = blk / sub;
+  const GemmTask t = tasks[task];
+  if (t.i == t.j && bn > bm) return;
+  if (*tv.info) return;
+
+  const void* Ap = tv.tile(t.i, k);
+  const void* Bp = tv.tile(t.j, k);
+  const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lrow = tid & 127;   // loader row
+  const int lkg = tid >> 7;     // loader k group: k = 8 lkg + 16 g .. +7
+  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
+
+  u16x8 ra[4], rb[4];
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int64_t col = kk + 8 * lkg + 16 * g + e;
+        ra[g][e] = load_as<CF>(Ap, fa, col * nb + arow0 + lrow);
+        rb[g][e] = load_as<CF>(Bp, fb, col * nb + brow0 + lrow);
+      }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      *(u16x8*)&As[lrow][8 * lkg + 16 * g] = ra[g];
+      *(u16x8*)&Bs[lrow][8 * lkg + 16 * g] = rb[g];
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+  gload(0);
+  for (int kk = 0; kk < nb; kk += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (kk + BK < nb) gload(kk + BK);
+#pragma unroll
+    for (int k32 = 0; k32 < BK; k32 += 32) {
+      u16x8 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = *(const u16x8*)&As[wm * 64 + a * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = *(const u16x8*)&Bs[wn * 64 + b * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (CF == BF16)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[a]),
+                                                                 __builtin_bit_cast(bf16x8, bv[b]), acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av[a]),
+                                                                __builtin_bit_cast(f16x8, bv[b]), acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+
+  void* Cp = tv.tile(t.i, t.j);
+  const int fc = tv.tfmt(t.i, t.j);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int64_t R = arow0 + wm * 64 + a * 16 + 4 * (lane >> 4) + r;
+        int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
+        int64_t idx = C * nb + R;
+        double c = load_wide(Cp, fc, idx) - (double)acc[a][b][r];
+        store_round(Cp, fc, idx, c);
+      }
+}
+
+hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
+                              hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  const int sub = tv.nb / UBM;
+  dim3 grid(ntasks * sub * sub);
+  switch (cfmt) {
+    case F64: k_update_kmajor<F64><<<grid, 256, 0, s>>>(tv, k, tasks); break;
+    case F32: k_update_kmajor<F32><<<grid, 256, 0, s>>>(tv, k, tasks); break;
+    case BF16: k_update_mmajor<BF16><<<grid, 256, 0, s>>>(tv, k, tasks); break;
+    case F16: k_update_mmajor<F16><<<grid, 256, 0, s>>>(tv, k, tasks); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// POTRF of the FP64 diagonal tile k (left-looking over 32-column panels, one
+// workgroup).  Per panel J: (1) A[J0:, J] -= L[J0:, :J0] L[J, :J0]^T with FP64
+// MFMA straight from the tile, (2) unblocked Cholesky of the 32 x 32 diagonal
+// block in LDS, (3) the rows below solved against it by substitution.
+// ---------------------------------------------------------------------------
+constexpr int PW = 32;
+
+__global__ __launch_bounds__(256) void k_potrf(TileView tv, int k) {
+  if (*tv.info) return;
+  const int nb = tv.nb;
+  double* A = (double*)tv.tile(k, k);
+  __shared__ double D[PW][PW + 1];
+  __shared__ double Xs[256][PW + 1];
+  __shared__ int fail;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) fail = 0;
+
+  for (int J0 = 0; J0 < nb; J0 += PW) {
+    // (1) panel update with the columns already factored
+    if (J0 > 0) {
+      const int nrb = (nb - J0) / 16;  // 16-row blocks from J0 down
+      for (int rb = wave; rb < nrb; rb += 4) {
+        const int R0 = J0 + rb * 16;
+        d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        for (int kk = 0; kk < J0; kk += 4) {
+          const int64_t col = kk + (lane >> 4);
+          double a = A[col * nb + R0 + (lane & 15)];
+          double b0 = A[col * nb + J0 + (lane & 15)];
+          double b1 = A[col * nb + J0 + 16 + (lane & 15)];
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int R = R0 + (lane >> 4) + 4 * r;
+          const int c = lane & 15;
+          if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc0[r];
+          if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= acc1[r];
+        }
+      }
+    }
+    __syncthreads();
+    // (2) diagonal 32 x 32 block
+    for (int e = tid; e < PW * PW; e += 256) {
+      int r = e % PW, c = e / PW;
+      D[r][c] = (r >= c) ? A[(int64_t)(J0 + c) * nb + J0 + r] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < PW; ++c) {
+      if (tid == 0) {
+        double d = D[c][c];
+        if (!(d > 0.0)) {
+          fail = 1;
+          if (*tv.info == 0) *tv.info = k * nb + J0 + c + 1;
+        }
+        D[c][c] = sqrt(d);
+      }
+      __syncthreads();
+      if (fail) return;
+      const double piv = D[c][c];
+      if (tid > c && tid < PW) D[tid][c] /= piv;
+      __syncthreads();
+      for (int e = tid; e < PW * PW; e += 256) {
+        int r = e % PW, q = e / PW;
+        if (q > c && r >= q) D[r][q] -= D[r][c] * D[q][c];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < PW * PW; e += 256) {
+      int r = e % PW, c = e / PW;
+      if (r >= c) A[(int64_t)(J0 + c) * nb + J0 + r] = D[r][c];
+    }
+    // (3) rows below: x L_JJ^T = a, one row per thread, the row kept in LDS
+    for (int R0 = J0 + PW; R0 < nb; R0 += 256) {
+      const int R = R0 + tid;
+      if (R < nb) {
+        for (int c = 0; c < PW; ++c) Xs[tid][c] = A[(int64_t)(J0 + c) * nb + R];
+        for (int c = 0; c < PW; ++c) {
+          double v = Xs[tid][c];
+          for (int m = 0; m < c; ++m) v -= Xs[tid][m] * D[c][m];
+          Xs[tid][c] = v / D[c][c];
+        }
+        for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + R] = Xs[tid][c];
+      }
+    }
+    __syncthreads();
+  }
+  // zero the strictly upper triangle so the stored tile is exactly L_kk
+  for (int64_t e = tid; e < (int64_t)nb * nb; e += 256) {
+    int r = (int)(e % nb), c = (int)(e / nb);
+    if (r < c) A[e] = 0.0;
+  }
+}
+
+hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
+  k_potrf<<<1, 256, 0, s>>>(tv, k);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Panel TRSM: for i > k, X = A_ik L_kk^{-T} in FP64, rounded once to p(i,k).
+// One workgroup per 64 rows of one panel tile; left-looking over 32-column
+// chunks with the FP64 X kept in a workspace (ws: (nt-k-1) tiles of nb x nb).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
+  if (*tv.info) return;
+  const int nb = tv.nb;
+  const int rblocks = nb / 64;
+  const int ti = k + 1 + blockIdx.x / rblocks;
+  const int r0 = (blockIdx.x % rblocks) * 64;
+  const double* Lkk = (const double*)tv.tile(k, k);
+  void* Ap = tv.tile(ti, k);
+  const int fa = tv.tfmt(ti, k);
+  double* X = ws + (int64_t)(ti - k - 1) * nb * nb;  // column-major nb x nb, rows r0..r0+63 owned here
+  __shared__ double T[64][PW + 1];
+  __shared__ double D[PW][PW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int J0 = 0; J0 < nb; J0 += PW) {
+    // T = A[rows, J] - X[rows, :J0] L[J, :J0]^T ; wave w owns rows 16w .. 16w+15
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const int R0 = r0 + wave * 16;
+    for (int kk = 0; kk < J0; kk += 4) {
+      const int64_t col = kk + (lane >> 4);
+      double a = X[col * nb + R0 + (lane & 15)];
+      double b0 = Lkk[col * nb + J0 + (lane & 15)];
+      double b1 = Lkk[col * nb + J0 + 16 + (lane & 15)];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lr = wave * 16 + (lane >> 4) + 4 * r;
+      const int c = lane & 15;
+      T[lr][c] = load_wide(Ap, fa, (int64_t)(J0 + c) * nb + r0 + lr) - acc0[r];
+      T[lr][c + 16] = load_wide(Ap, fa, (int64_t)(J0 + c + 16) * nb + r0 + lr) - acc1[r];
+    }
+    for (int e = tid; e < PW * PW; e += 256) {
+      int r = e % PW, c = e / PW;
+      D[r][c] = Lkk[(int64_t)(J0 + c) * nb + J0 + r];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double x[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        double v = T[tid][c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
+        x[c] = v / D[c][c];
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) X[(int64_t)(J0 + c) * nb + r0 + tid] = x[c];
+    }
+    __syncthreads();
+  }
+  // single rounding into the tile's own format
+  for (int e = tid; e < 64 * nb; e += 256) {
+    int r = e % 64, c = e / 64;
+    int64_t idx = (int64_t)c * nb + r0 + r;
+    store_round(Ap, fa, idx, X[idx]);
+  }
+}
+
+hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, hipStream_t s) {
+  int ntile = tv.nt - k - 1;
+  if (ntile <= 0) return hipSuccess;
+  k_trsm<<<ntile * (tv.nb / 64), 256, 0, s>>>(tv, k, ws);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// log|Sigma| = 2 sum_i log L_ii over the first n diagonal entries; fixed
+// summation order (strided per thread, then a fixed tree).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_logdet(TileView tv, double* out) {
+  __shared__ double red[256];
+  const int nb = tv.nb;
+  double s = 0.0;
+  if (*tv.info == 0) {
+    for (int g = threadIdx.x; g < tv.n; g += 256) {
+      int t = g / nb, l = g % nb;
+      s += log(((const double*)tv.tile(t, t))[(int64_t)l * nb + l]);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = 2.0 * red[0];
+}
+
+hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s) {
+  k_logdet<<<1, 256, 0, s>>>(tv, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Inverse of every diagonal tile, Linv_kk = L_kk^{-1} (lower, FP64), used by the
+// tile solves.  One workgroup per (tile, 32-column block J): block column J of
+// the inverse is the forward substitution L X = E_J, swept down the 32-row
+// blocks: X_IJ = D_I^{-1} (E_IJ - sum_{J <= M < I} L_IM X_MJ).
+// Linv (nt tiles, nb x nb column-major) and LinvT (their transposes) are written.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trtri(TileView tv, double* Linv, double* LinvT) {
+  if (*tv.info) return;
+  const int nb = tv.nb, nbl = nb / PW;
+  const int kt = blockIdx.x / nbl;
+  const int J = blockIdx.x % nbl, J0 = J * PW;
+  const double* L = (const double*)tv.tile(kt, kt);
+  double* X = Linv + (int64_t)kt * nb * nb;
+  double* XT = LinvT + (int64_t)kt * nb * nb;
+  __shared__ double T[PW][PW + 1];
+  __shared__ double D[PW][PW + 1];
+  const int tid = threadIdx.x;
+  const int orow = tid % PW, ocol0 = (tid / PW) * 4;  // each thread: 1 row x 4 columns of the block
+
+  // zero the strictly upper part of block column J
+  for (int e = tid; e < J0 * PW; e += 256) {
+    int r = e % J0, c = e / J0;
+    X[(int64_t)(J0 + c) * nb + r] = 0.0;
+    XT[(int64_t)r * nb + J0 + c] = 0.0;
+  }
+  for (int I0 = J0; I0 < nb; I0 += PW) {
+    double acc[4] = {0, 0, 0, 0};
+    for (int m = J0; m < I0; ++m) {
+      double l = L[(int64_t)m * nb + I0 + orow];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += l * X[(int64_t)(J0 + ocol0 + q) * nb + m];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double e = (I0 == J0 && orow == ocol0 + q) ? 1.0 : 0.0;
+      T[orow][ocol0 + q] = e - acc[q];
+    }
+    for (int e = tid; e < PW * PW; e += 256) {
+      int r = e % PW, c = e / PW;
+      D[r][c] = L[(int64_t)(I0 + c) * nb + I0 + r];
+    }
+    __syncthreads();
+    if (tid < PW) {  // column tid of the block: D x = t
+      double x[PW];
+#pragma unroll
+      for (int r = 0; r < PW; ++r) {
+        double v = T[r][tid];
+#pragma unroll
+        for (int m = 0; m < r; ++m) v -= D[r][m] * x[m];
+        x[r] = v / D[r][r];
+      }
+#pragma unroll
+      for (int r = 0; r < PW; ++r) {
+        X[(int64_t)(J0 + tid) * nb + I0 + r] = x[r];
+        XT[(int64_t)(I0 + r) * nb + J0 + tid] = x[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_trtri_diag(const TileView& tv, double* Linv, hipStream_t s) {
+  const int64_t tile = (int64_t)tv.nb * tv.nb;
+  k_trtri<<<tv.nt * (tv.nb / PW), 256, 0, s>>>(tv, Linv, Linv + (int64_t)tv.nt * tile);
+  return hipGetLastError();
+}
+
+}  // namespace mpcr

@@ -1,0 +1,213 @@
+// Internal declarations of the mpcr HIP library (gfx950 only).
+//
+// Formats: the device rounding functions take an FP64 value and round it ONCE
+// to the target with round-to-nearest-even.  FP64 -> FP32 is the hardware
+// conversion (v_cvt_f32_f64, RNE).  For the narrower formats the value is
+// first rounded to FP32 by round-to-odd (truncate, then set the last bit when
+// inexact) and then rounded to nearest-even to the target; because every
+// target keeps at most 11 significand bits and FP32 keeps 24 >= 11 + 2, the
+// two steps give the correctly rounded result (Boldo & Melquiond, "When double
+// rounding is odd", 2005).  FP8-E4M3FN conversions saturate at +-448.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpcr.h"
+
+namespace mpcr {
+
+enum Fmt : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, F8 = 4 };
+
+__host__ __device__ inline int fmt_bytes(int f) {
+  return f == F64 ? 8 : (f == F32 ? 4 : (f == F8 ? 1 : 2));
+}
+
+// Unit roundoff 2^-t of each format (t = significand bits incl. implicit bit).
+__host__ __device__ inline double fmt_unit_roundoff(int f) {
+  return f == F64 ? 0x1p-53 : f == F32 ? 0x1p-24 : f == F16 ? 0x1p-11 : f == BF16 ? 0x1p-8 : 0x1p-4;
+}
+
+// ---------------------------------------------------------------------------
+// device rounding / widening
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float round_odd_f32(double x) {
+  float t = __double2float_rz(x);
+  if ((double)t != x) t = __uint_as_float(__float_as_uint(t) | 1u);
+  return t;
+}
+
+__device__ __forceinline__ float to_f32(double x) { return (float)x; }
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint16_t to_bf16(double x) { return f32_to_bf16_rne(round_odd_f32(x)); }
+
+__device__ __forceinline__ uint16_t to_f16(double x) {
+  _Float16 h = (_Float16)round_odd_f32(x);  // v_cvt_f16_f32, round-to-nearest-even
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+// FP32 -> FP8-E4M3FN (bias 7, 3 stored significand bits, subnormal quantum
+// 2^-9, largest finite 448 = 0x7e), nearest-even, saturating.
+__device__ __forceinline__ uint8_t f32_to_e4m3_sat(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  uint32_t a = u & 0x7fffffffu;
+  if (a > 0x7f800000u) return 0x7f;                   // NaN
+  if (a >= 0x43e00000u) return sign | 0x7e;           // |f| >= 448 (incl. inf): saturate
+  if (a < 0x3c800000u) {                              // |f| < 2^-6: subnormal range
+    float q = __uint_as_float(a) * 512.0f;            // in units of 2^-9, exact
+    float r = __builtin_rintf(q);                     // ties to even, 0..8
+    return sign | (uint8_t)r;                         // r == 8 is the smallest normal 0x08
+  }
+  uint32_t e = (a >> 23) - 127u + 7u;                 // biased FP8 exponent, 1..15
+  uint32_t m = a & 0x7fffffu;
+  uint32_t r = m + 0x7ffffu + ((m >> 20) & 1u);       // round 23 -> 3 bits, ties to even
+  if (r & 0x800000u) { e += 1; r = 0; }
+  uint32_t code = (e << 3) | ((r >> 20) & 7u);
+  if (code > 0x7e) code = 0x7e;
+  return sign | (uint8_t)code;
+}
+
+__device__ __forceinline__ uint8_t to_e4m3(double x) { return f32_to_e4m3_sat(round_odd_f32(x)); }
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float f16_to_f32(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+__device__ __forceinline__ float e4m3_to_f32(uint8_t c) {
+  uint32_t s = (c & 0x80u) << 24;
+  uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  if (e == 15u && m == 7u) return __uint_as_float(0x7fc00000u | s);
+  float v = e == 0 ? (float)m * 0x1p-9f : __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return __uint_as_float(__float_as_uint(v) | s);
+}
+
+// Load element `idx` of a buffer of format f, widened to double (exact).
+__device__ __forceinline__ double load_wide(const void* p, int f, int64_t idx) {
+  switch (f) {
+    case F64: return ((const double*)p)[idx];
+    case F32: return (double)((const float*)p)[idx];
+    case F16: return (double)f16_to_f32(((const uint16_t*)p)[idx]);
+    case BF16: return (double)bf16_to_f32(((const uint16_t*)p)[idx]);
+    default: return (double)e4m3_to_f32(((const uint8_t*)p)[idx]);
+  }
+}
+
+// Store x rounded once to format f.
+__device__ __forceinline__ void store_round(void* p, int f, int64_t idx, double x) {
+  switch (f) {
+    case F64: ((double*)p)[idx] = x; break;
+    case F32: ((float*)p)[idx] = to_f32(x); break;
+    case F16: ((uint16_t*)p)[idx] = to_f16(x); break;
+    case BF16: ((uint16_t*)p)[idx] = to_bf16(x); break;
+    default: ((uint8_t*)p)[idx] = to_e4m3(x); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile store: lower tiles (i >= j) of an nt x nt tiling, each tile nb x nb
+// column-major and contiguous in its own format; packed index
+// t(i, j) = i (i + 1) / 2 + j.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline int64_t tri_index(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+
+struct TileView {
+  uint8_t* base;          // device base address of all tiles
+  const int64_t* off;     // device: byte offset of tile t(i, j)
+  const uint8_t* fmt;     // device: format of tile t(i, j)
+  int nb;
+  int nt;
+  int n;                  // true (unpadded) order
+  int* info;              // device: 0, or 1-based global column of a failed pivot
+
+  __device__ __forceinline__ void* tile(int i, int j) const { return base + off[tri_index(i, j)]; }
+  __device__ __forceinline__ int tfmt(int i, int j) const { return fmt[tri_index(i, j)]; }
+};
+
+struct GemmTask {
+  int i, j;  // output tile (i, j); operands are tiles (i, k) and (j, k)
+};
+
+}  // namespace mpcr
+
+// ---------------------------------------------------------------------------
+// kernel launchers (defined in the .hip files, called by the host driver)
+// ---------------------------------------------------------------------------
+namespace mpcr {
+
+hipError_t launch_tiles_from_dense(const TileView& tv, const double* A, int64_t lda, hipStream_t s);
+hipError_t launch_tiles_from_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
+                                        hipStream_t s);
+hipError_t launch_tiles_to_dense(const TileView& tv, double* L, int64_t ldl, hipStream_t s);
+hipError_t launch_covariance_dense(int n, const double* locs, const mpcr_theta_t& th, double* A,
+                                   int64_t lda, hipStream_t s);
+hipError_t launch_covariance_tile_amax(int n, int nb, const double* locs, const mpcr_theta_t& th,
+                                       double* amax /* device nt*nt */, hipStream_t s);
+hipError_t launch_convert(int prec, int64_t m, int64_t n, const double* src, int64_t lds, void* dst,
+                          int64_t ldd, int8_t* scale_exp, hipStream_t s);
+
+hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s);
+hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, hipStream_t s);
+hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
+                              hipStream_t s);
+hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s);
+hipError_t launch_trtri_diag(const TileView& tv, double* Linv, hipStream_t s);
+
+hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W,
+                           int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
+                             hipStream_t s);
+hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* X,
+                           int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_bwd_update(const TileView& tv, int k, double* R, const double* X, int64_t ld, int nrhs,
+                             hipStream_t s);
+
+hipError_t launch_residual_cov(int n, const double* locs, const mpcr_theta_t& th, const double* B,
+                               const double* X, double* R, int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_residual_dense(int n, const double* A, int64_t lda, const double* B, const double* X,
+                                 double* R, int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_rowsum_abs_cov(int n, const double* locs, const mpcr_theta_t& th, double* out,
+                                 hipStream_t s);
+hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* out, hipStream_t s);
+
+// column reductions over the first n rows of n x nrhs blocks (ld), deterministic
+hipError_t launch_col_dot(int n, int nrhs, const double* A, const double* B, int64_t ld, double* partial,
+                          double* out, hipStream_t s);
+hipError_t launch_col_stats(int n, int nrhs, const double* R, const double* X, const double* B, int64_t ld,
+                            const double* sig_inf, double* partial, double* stats, hipStream_t s);
+hipError_t launch_max_reduce(int n, const double* v, double* partial, double* out, hipStream_t s);
+
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_copy_cols(int n, int nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,
+                            hipStream_t s);
+hipError_t launch_axpy_cols(int n, int nrhs, const double* alpha, double sign, const double* X, double* Y,
+                            int64_t ld, hipStream_t s);
+hipError_t launch_xpby_cols(int n, int nrhs, const double* X, const double* beta, double* Y, int64_t ld,
+                            hipStream_t s);
+hipError_t launch_pcg_alpha(int nrhs, const double* rz, const double* pq, const int* active, double* alpha,
+                            hipStream_t s);
+hipError_t launch_pcg_beta(int nrhs, const double* rz_new, double* rz, const int* active, double* beta,
+                           hipStream_t s);
+hipError_t launch_loglik(int n, int nrhs, const double* logdet, const double* quad, double* out,
+                         hipStream_t s);
+hipError_t launch_quad_refined(int n, int nrhs, const double* Z, const double* X, const double* R, int64_t ld,
+                               double* partial, double* quad, hipStream_t s);
+
+hipError_t launch_morton_codes(int n, const double* locs, uint64_t* keys, int npow2, hipStream_t s);
+hipError_t launch_bitonic_sort(uint64_t* keys, int npow2, hipStream_t s);
+hipError_t launch_keys_to_perm(int n, const uint64_t* keys, int64_t* perm, hipStream_t s);
+hipError_t launch_gather_rows(int n, int ncols, const double* src, int64_t lds, const int64_t* perm,
+                              double* dst, int64_t ldd, hipStream_t s);
+
+hipError_t launch_gemm(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha,
+                       const void* A, int64_t lda, const int8_t* sA, const void* B, int64_t ldb,
+                       const int8_t* sB, double beta, void* C, int64_t ldc, int cprec, hipStream_t s);
+
+}  // namespace mpcr

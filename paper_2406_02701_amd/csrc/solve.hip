@@ -1,0 +1,514 @@
+// Tile triangular solves, FP64 residuals and the refinement vector kernels.
+//
+// Forward solve L W = B and backward solve L^T X = W over the tile factor (the
+// paper's forwardsolve / backsolve pair of the MLE section), with the inverted
+// FP64 diagonal tiles:
+//   forward,  k = 0 .. nt-1:  W_k = Linv_kk R_k ;  R_i -= L_ik W_k   (i > k)
+//   backward, k = nt-1 .. 0:  X_k = Linv_kk^T V_k ; V_i -= L_ki^T X_k (i < k)
+// Off-diagonal tiles are read in their storage format and widened to FP64.
+// All right-hand-side blocks are column-major with leading dimension ld >= the
+// padded order nt*nb; padded rows are kept at zero.
+#include "mpcr_internal.h"
+
+namespace mpcr {
+
+constexpr int RHS_CHUNK = 16;
+
+// out[r0 .. r0+63][c] (op) M[rows][0..nb) * V[0..nb)[c], M an nb x nb column-major
+// tile of format f.  mode 0: out = M V ; mode 1: out -= M V.  Thread (r, cq)
+// handles row r and columns cq, cq+4, cq+8, cq+12 of each 16-column chunk.
+__device__ void tile_gemv_n(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
+                            int64_t ldo, int nrhs, int mode, double* Vs /* LDS nb_chunk x 16 */) {
+  const int tid = threadIdx.x, r = tid & 63, cq = tid >> 6;
+  constexpr int KC = 256;
+  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+    double acc[4] = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < nb; k0 += KC) {
+      const int kc = (nb - k0) < KC ? (nb - k0) : KC;
+      __syncthreads();
+      for (int e = tid; e < KC * RHS_CHUNK; e += 256) {
+        int kk = e % KC, c = e / KC;
+        Vs[c * KC + kk] = (kk < kc && c0 + c < nrhs) ? V[(int64_t)(c0 + c) * ldv + k0 + kk] : 0.0;
+      }
+      __syncthreads();
+      for (int kk = 0; kk < kc; ++kk) {
+        double m = load_wide(M, f, (int64_t)(k0 + kk) * nb + r0 + r);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += m * Vs[(cq + 4 * q) * KC + kk];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int c = c0 + cq + 4 * q;
+      if (c < nrhs) {
+        double* o = out + (int64_t)c * ldo + r0 + r;
+        *o = mode == 0 ? acc[q] : *o - acc[q];
+      }
+    }
+  }
+}
+
+// out[r0 .. r0+63][c] (op) M^T[rows][...] V.  Thread (r, part) walks column r0+r of M
+// with stride 4 in k (4 consecutive threads read 32 consecutive bytes); the four
+// partial sums are combined in a fixed order through LDS.
+__device__ void tile_gemv_t(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
+                            int64_t ldo, int nrhs, int mode, double* Vs, double* part /* LDS 256 x 16 */) {
+  const int tid = threadIdx.x, r = tid >> 2, p = tid & 3;
+  constexpr int KC = 256;
+  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+    double acc[RHS_CHUNK];
+#pragma unroll
+    for (int q = 0; q < RHS_CHUNK; ++q) acc[q] = 0.0;
+    for (int k0 = 0; k0 < nb; k0 += KC) {
+      const int kc = (nb - k0) < KC ? (nb - k0) : KC;
+      __syncthreads();
+      for (int e = tid; e < KC * RHS_CHUNK; e += 256) {
+        int kk = e % KC, c = e / KC;
+        Vs[kk * RHS_CHUNK + c] = (kk < kc && c0 + c < nrhs) ? V[(int64_t)(c0 + c) * ldv + k0 + kk] : 0.0;
+      }
+      __syncthreads();
+      for (int kk = p; kk < kc; kk += 4) {
+        double m = load_wide(M, f, (int64_t)(r0 + r) * nb + k0 + kk);
+#pragma unroll
+        for (int q = 0; q < RHS_CHUNK; ++q) acc[q] += m * Vs[kk * RHS_CHUNK + q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RHS_CHUNK; ++q) part[tid * RHS_CHUNK + q] = acc[q];
+    __syncthreads();
+    for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
+      int rr = e % 64, q = e / 64;
+      int c = c0 + q;
+      if (c < nrhs) {
+        const double* ps = part + (rr * 4) * RHS_CHUNK + q;
+        double s = ((ps[0] + ps[RHS_CHUNK]) + ps[2 * RHS_CHUNK]) + ps[3 * RHS_CHUNK];
+        double* o = out + (int64_t)c * ldo + r0 + rr;
+        *o = mode == 0 ? s : *o - s;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fwd_diag(int nb, const double* Linv, int k, const double* R, double* W,
+                                                  int64_t ld, int nrhs, const int* info) {
+  if (*info) return;
+  __shared__ double Vs[256 * RHS_CHUNK];
+  const int r0 = blockIdx.x * 64;
+  const int64_t off = (int64_t)k * nb;
+  tile_gemv_n(Linv + (int64_t)k * nb * nb, F64, nb, r0, R + off, ld, W + off, ld, nrhs, 0, Vs);
+}
+
+__global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
+                                                    int nrhs) {
+  if (*tv.info) return;
+  __shared__ double Vs[256 * RHS_CHUNK];
+  const int nb = tv.nb, rb = nb / 64;
+  const int i = k + 1 + blockIdx.x / rb;
+  const int r0 = (blockIdx.x % rb) * 64;
+  tile_gemv_n(tv.tile(i, k), tv.tfmt(i, k), nb, r0, W + (int64_t)k * nb, ld, R + (int64_t)i * nb, ld, nrhs, 1,
+              Vs);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_diag(int nb, int nt, const double* Linv, int k, const double* V,
+                                                  double* X, int64_t ld, int nrhs, const int* info) {
+  if (*info) return;
+  __shared__ double Vs[256 * RHS_CHUNK];
+  const int r0 = blockIdx.x * 64;
+  const int64_t off = (int64_t)k * nb;
+  const double* LinvT = Linv + (int64_t)nt * nb * nb + (int64_t)k * nb * nb;
+  tile_gemv_n(LinvT, F64, nb, r0, V + off, ld, X + off, ld, nrhs, 0, Vs);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
+                                                    int nrhs) {
+  if (*tv.info) return;
+  __shared__ double Vs[256 * RHS_CHUNK];
+  __shared__ double part[256 * RHS_CHUNK];
+  const int nb = tv.nb, rb = nb / 64;
+  const int i = blockIdx.x / rb;  // i < k
+  const int r0 = (blockIdx.x % rb) * 64;
+  tile_gemv_t(tv.tile(k, i), tv.tfmt(k, i), nb, r0, X + (int64_t)k * nb, ld, V + (int64_t)i * nb, ld, nrhs, 1, Vs,
+              part);
+}
+
+hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
+                           int nrhs, hipStream_t s) {
+  k_fwd_diag<<<tv.nb / 64, 256, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
+  return hipGetLastError();
+}
+hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
+                             hipStream_t s) {
+  int nt = tv.nt - k - 1;
+  if (nt <= 0) return hipSuccess;
+  k_fwd_update<<<nt * (tv.nb / 64), 256, 0, s>>>(tv, k, R, W, ld, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
+                           int nrhs, hipStream_t s) {
+  k_bwd_diag<<<tv.nb / 64, 256, 0, s>>>(tv.nb, tv.nt, Linv, k, V, X, ld, nrhs, tv.info);
+  return hipGetLastError();
+}
+hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* X, int64_t ld, int nrhs,
+                             hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  k_bwd_update<<<k * (tv.nb / 64), 256, 0, s>>>(tv, k, V, X, ld, nrhs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual R = B - Sigma X over the first n rows (matrix-free: Sigma's
+// entries regenerated from the sites), and ||Sigma||_inf row sums.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double matern_corr_s(double x, int nuc) {
+  double e = exp(-x);
+  if (nuc == 0) return e;
+  if (nuc == 1) return (1.0 + x) * e;
+  return (1.0 + x + x * x / 3.0) * e;
+}
+
+static int nu_code_s(double nu) { return nu == 0.5 ? 0 : (nu == 1.5 ? 1 : 2); }
+
+// One workgroup per 64 rows; thread (r, q) sums columns q, q+4, ... of each
+// 256-column chunk; the four partials are combined in a fixed order.
+// MODE 0: R = B - Sigma X (B == NULL: R = -Sigma X) ; MODE 1: R[:,0] = sum_c |Sigma_rc|.
+// DENSE: Sigma read from the FP64 matrix A instead of regenerated from the sites.
+template <int MODE, bool DENSE>
+__global__ __launch_bounds__(256) void k_sigma_apply(int n, const double* locs, double s2, double range, int nuc,
+                                                     double nugget, const double* A, int64_t lda, const double* B,
+                                                     const double* X, double* R, int64_t ld, int nrhs) {
+  constexpr int CC = 256;
+  __shared__ double Ls[2][CC];
+  __shared__ double Xs[CC * RHS_CHUNK];
+  __shared__ double part[4][64][RHS_CHUNK + 1];
+  const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
+  const int row = blockIdx.x * 64 + r;
+  const bool live = row < n;
+  double px = 0, py = 0;
+  if (!DENSE && live) { px = locs[row]; py = locs[n + row]; }
+  const int ncol = MODE == 1 ? 1 : nrhs;
+  for (int c0 = 0; c0 < ncol; c0 += RHS_CHUNK) {
+    double acc[RHS_CHUNK];
+#pragma unroll
+    for (int j = 0; j < RHS_CHUNK; ++j) acc[j] = 0.0;
+    for (int k0 = 0; k0 < n; k0 += CC) {
+      __syncthreads();
+      for (int e = tid; e < CC; e += 256) {
+        int c = k0 + e;
+        if (!DENSE) {
+          Ls[0][e] = c < n ? locs[c] : 0.0;
+          Ls[1][e] = c < n ? locs[n + c] : 0.0;
+        }
+      }
+      if (MODE == 0)
+        for (int e = tid; e < CC * RHS_CHUNK; e += 256) {
+          int kk = e % CC, j = e / CC;
+          Xs[kk * RHS_CHUNK + j] = (k0 + kk < n && c0 + j < nrhs) ? X[(int64_t)(c0 + j) * ld + k0 + kk] : 0.0;
+        }
+      __syncthreads();
+      if (live) {
+        const int kend = (n - k0) < CC ? (n - k0) : CC;
+        for (int kk = q; kk < kend; kk += 4) {
+          const int col = k0 + kk;
+          double sv;
+          if (DENSE) {
+            sv = A[(int64_t)col * lda + row];
+          } else {
+            double dx = px - Ls[0][kk], dy = py - Ls[1][kk];
+            sv = s2 * matern_corr_s(sqrt(dx * dx + dy * dy) / range, nuc);
+            if (col == row) sv += nugget;
+          }
+          if (MODE == 1) {
+            acc[0] += fabs(sv);
+          } else {
+#pragma unroll
+            for (int j = 0; j < RHS_CHUNK; ++j) acc[j] += sv * Xs[kk * RHS_CHUNK + j];
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RHS_CHUNK; ++j) part[q][r][j] = acc[j];
+    __syncthreads();
+    for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
+      int rr = e % 64, j = e / 64;
+      int grow = blockIdx.x * 64 + rr, c = c0 + j;
+      if (grow < n && c < ncol) {
+        double s = ((part[0][rr][j] + part[1][rr][j]) + part[2][rr][j]) + part[3][rr][j];
+        if (MODE == 1)
+          R[grow] = s;
+        else
+          R[(int64_t)c * ld + grow] = (B ? B[(int64_t)c * ld + grow] : 0.0) - s;
+      }
+    }
+  }
+}
+
+hipError_t launch_residual_cov(int n, const double* locs, const mpcr_theta_t& th, const double* B, const double* X,
+                               double* R, int64_t ld, int nrhs, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_sigma_apply<0, false><<<(n + 63) / 64, 256, 0, s>>>(n, locs, th.sigma2, th.range, nu_code_s(th.nu), th.nugget,
+                                                        nullptr, 0, B, X, R, ld, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_residual_dense(int n, const double* A, int64_t lda, const double* B, const double* X, double* R,
+                                 int64_t ld, int nrhs, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_sigma_apply<0, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, B, X, R, ld, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_rowsum_abs_cov(int n, const double* locs, const mpcr_theta_t& th, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_sigma_apply<1, false><<<(n + 63) / 64, 256, 0, s>>>(n, locs, th.sigma2, th.range, nu_code_s(th.nu), th.nugget,
+                                                        nullptr, 0, nullptr, nullptr, out, 0, 1);
+  return hipGetLastError();
+}
+hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_sigma_apply<1, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, nullptr, nullptr, out, 0, 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// deterministic column reductions: stage 1 over fixed 1024-row slabs, stage 2
+// sums the slabs in order
+// ---------------------------------------------------------------------------
+constexpr int SLAB = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double s = red[0];
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ double block_max(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+// partial[slab][c] = sum over the slab of A[:,c] * B[:,c]
+__global__ __launch_bounds__(256) void k_col_dot_1(int n, const double* A, const double* B, int64_t ld,
+                                                   double* partial, int nslab) {
+  __shared__ double red[256];
+  const int slab = blockIdx.x, c = blockIdx.y;
+  double s = 0.0;
+  for (int r = slab * SLAB + threadIdx.x; r < n && r < (slab + 1) * SLAB; r += 256)
+    s += A[(int64_t)c * ld + r] * B[(int64_t)c * ld + r];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[(int64_t)c * nslab + slab] = s;
+}
+__global__ void k_col_sum_2(int nslab, int ncol, const double* partial, double* out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0;
+  for (int i = 0; i < nslab; ++i) s += partial[(int64_t)c * nslab + i];
+  out[c] = s;
+}
+
+hipError_t launch_col_dot(int n, int nrhs, const double* A, const double* B, int64_t ld, double* partial,
+                          double* out, hipStream_t s) {
+  int nslab = (n + SLAB - 1) / SLAB;
+  if (nslab == 0) nslab = 1;
+  k_col_dot_1<<<dim3(nslab, nrhs), 256, 0, s>>>(n, A, B, ld, partial, nslab);
+  k_col_sum_2<<<(nrhs + 63) / 64, 64, 0, s>>>(nslab, nrhs, partial, out);
+  return hipGetLastError();
+}
+
+// Per column: stats[c] = { ||R||_2^2, ||B||_2^2, max|R|, max|X|, max|B| } (5 x nrhs),
+// then eta = max|R| / (sig_inf max|X| + max|B|), rel2 = ||R|| / ||B|| in stats[5 nrhs + 2c .. ].
+__global__ __launch_bounds__(256) void k_col_stats_1(int n, const double* R, const double* X, const double* B,
+                                                     int64_t ld, double* partial, int nslab) {
+  __shared__ double red[256];
+  const int slab = blockIdx.x, c = blockIdx.y;
+  double rr = 0, bb = 0, mr = 0, mx = 0, mb = 0;
+  for (int r = slab * SLAB + threadIdx.x; r < n && r < (slab + 1) * SLAB; r += 256) {
+    double a = R[(int64_t)c * ld + r], x = X[(int64_t)c * ld + r], b = B[(int64_t)c * ld + r];
+    rr += a * a;
+    bb += b * b;
+    mr = fmax(mr, fabs(a));
+    mx = fmax(mx, fabs(x));
+    mb = fmax(mb, fabs(b));
+  }
+  rr = block_sum(rr, red);
+  bb = block_sum(bb, red);
+  mr = block_max(mr, red);
+  mx = block_max(mx, red);
+  mb = block_max(mb, red);
+  if (threadIdx.x == 0) {
+    double* p = partial + ((int64_t)c * nslab + slab) * 5;
+    p[0] = rr; p[1] = bb; p[2] = mr; p[3] = mx; p[4] = mb;
+  }
+}
+__global__ void k_col_stats_2(int nslab, int ncol, const double* partial, const double* sig_inf, double* stats) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double rr = 0, bb = 0, mr = 0, mx = 0, mb = 0;
+  for (int i = 0; i < nslab; ++i) {
+    const double* p = partial + ((int64_t)c * nslab + i) * 5;
+    rr += p[0]; bb += p[1];
+    mr = fmax(mr, p[2]); mx = fmax(mx, p[3]); mb = fmax(mb, p[4]);
+  }
+  double den = (*sig_inf) * mx + mb;
+  stats[2 * c] = den > 0 ? mr / den : 0.0;               // eta
+  stats[2 * c + 1] = bb > 0 ? sqrt(rr) / sqrt(bb) : 0.0;  // ||r||_2 / ||b||_2
+}
+
+hipError_t launch_col_stats(int n, int nrhs, const double* R, const double* X, const double* B, int64_t ld,
+                            const double* sig_inf, double* partial, double* stats, hipStream_t s) {
+  int nslab = (n + SLAB - 1) / SLAB;
+  if (nslab == 0) nslab = 1;
+  k_col_stats_1<<<dim3(nslab, nrhs), 256, 0, s>>>(n, R, X, B, ld, partial, nslab);
+  k_col_stats_2<<<(nrhs + 63) / 64, 64, 0, s>>>(nslab, nrhs, partial, sig_inf, stats);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_max_1(int n, const double* v, double* partial) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int r = blockIdx.x * SLAB + threadIdx.x; r < n && r < (int)(blockIdx.x + 1) * SLAB; r += 256)
+    m = fmax(m, v[r]);
+  m = block_max(m, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+__global__ void k_max_2(int nslab, const double* partial, double* out) {
+  if (threadIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < nslab; ++i) m = fmax(m, partial[i]);
+  *out = m;
+}
+hipError_t launch_max_reduce(int n, const double* v, double* partial, double* out, hipStream_t s) {
+  int nslab = (n + SLAB - 1) / SLAB;
+  if (nslab == 0) nslab = 1;
+  k_max_1<<<nslab, 256, 0, s>>>(n, v, partial);
+  k_max_2<<<1, 64, 0, s>>>(nslab, partial, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers (columns of n x nrhs blocks, leading dimension ld)
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double* p, int64_t count, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  int64_t g = (count + 255) / 256;
+  k_fill<<<(unsigned)(g < 4096 ? g : 4096), 256, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_cols(int n, const double* src, int64_t lds, double* dst, int64_t ldd) {
+  const int c = blockIdx.y;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    dst[(int64_t)c * ldd + r] = src[(int64_t)c * lds + r];
+}
+hipError_t launch_copy_cols(int n, int nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,
+                            hipStream_t s) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  k_copy_cols<<<dim3(g < 256 ? g : 256, nrhs), 256, 0, s>>>(n, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+// Y[:,c] += sign * alpha[c] * X[:,c]
+__global__ void k_axpy_cols(int n, const double* alpha, double sign, const double* X, double* Y, int64_t ld) {
+  const int c = blockIdx.y;
+  const double a = sign * alpha[c];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    Y[(int64_t)c * ld + r] += a * X[(int64_t)c * ld + r];
+}
+hipError_t launch_axpy_cols(int n, int nrhs, const double* alpha, double sign, const double* X, double* Y,
+                            int64_t ld, hipStream_t s) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  k_axpy_cols<<<dim3(g < 256 ? g : 256, nrhs), 256, 0, s>>>(n, alpha, sign, X, Y, ld);
+  return hipGetLastError();
+}
+
+// Y[:,c] = X[:,c] + beta[c] * Y[:,c]
+__global__ void k_xpby_cols(int n, const double* X, const double* beta, double* Y, int64_t ld) {
+  const int c = blockIdx.y;
+  const double b = beta[c];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    Y[(int64_t)c * ld + r] = X[(int64_t)c * ld + r] + b * Y[(int64_t)c * ld + r];
+}
+hipError_t launch_xpby_cols(int n, int nrhs, const double* X, const double* beta, double* Y, int64_t ld,
+                            hipStream_t s) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  k_xpby_cols<<<dim3(g < 256 ? g : 256, nrhs), 256, 0, s>>>(n, X, beta, Y, ld);
+  return hipGetLastError();
+}
+
+// PCG step sizes; columns that are not active get 0 (they stay frozen).
+__global__ void k_pcg_alpha(int nrhs, const double* rz, const double* pq, const int* active, double* alpha) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  alpha[c] = (active[c] && pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
+}
+__global__ void k_pcg_beta(int nrhs, const double* rz_new, double* rz, const int* active, double* beta) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  double b = (active[c] && rz[c] != 0.0) ? rz_new[c] / rz[c] : 0.0;
+  beta[c] = b;
+  if (active[c]) rz[c] = rz_new[c];
+}
+hipError_t launch_pcg_alpha(int nrhs, const double* rz, const double* pq, const int* active, double* alpha,
+                            hipStream_t s) {
+  k_pcg_alpha<<<(nrhs + 63) / 64, 64, 0, s>>>(nrhs, rz, pq, active, alpha);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_beta(int nrhs, const double* rz_new, double* rz, const int* active, double* beta,
+                           hipStream_t s) {
+  k_pcg_beta<<<(nrhs + 63) / 64, 64, 0, s>>>(nrhs, rz_new, rz, active, beta);
+  return hipGetLastError();
+}
+
+// l = -(n/2) log(2 pi) - logdet/2 - quad_c/2  (MLE section of the paper)
+__global__ void k_loglik(int n, int nrhs, const double* logdet, const double* quad, double* out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  out[c] = -0.5 * (double)n * log(2.0 * M_PI) - 0.5 * (*logdet) - 0.5 * quad[c];
+}
+hipError_t launch_loglik(int n, int nrhs, const double* logdet, const double* quad, double* out, hipStream_t s) {
+  k_loglik<<<(nrhs + 63) / 64, 64, 0, s>>>(n, nrhs, logdet, quad, out);
+  return hipGetLastError();
+}
+
+// quad_c = z_c^T x_c + x_c^T r_c
+__global__ __launch_bounds__(256) void k_quad_1(int n, const double* Z, const double* X, const double* R, int64_t ld,
+                                                double* partial, int nslab) {
+  __shared__ double red[256];
+  const int slab = blockIdx.x, c = blockIdx.y;
+  double s = 0.0;
+  for (int r = slab * SLAB + threadIdx.x; r < n && r < (slab + 1) * SLAB; r += 256) {
+    double x = X[(int64_t)c * ld + r];
+    s += Z[(int64_t)c * ld + r] * x + x * R[(int64_t)c * ld + r];
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[(int64_t)c * nslab + slab] = s;
+}
+hipError_t launch_quad_refined(int n, int nrhs, const double* Z, const double* X, const double* R, int64_t ld,
+                               double* partial, double* quad, hipStream_t s) {
+  int nslab = (n + SLAB - 1) / SLAB;
+  if (nslab == 0) nslab = 1;
+  k_quad_1<<<dim3(nslab, nrhs), 256, 0, s>>>(n, Z, X, R, ld, partial, nslab);
+  k_col_sum_2<<<(nrhs + 63) / 64, 64, 0, s>>>(nslab, nrhs, partial, quad);
+  return hipGetLastError();
+}
+
+}  // namespace mpcr

@@ -1,0 +1,335 @@
+"""GPU parity of the tile Cholesky path against the oracle (through the C-ABI).
+
+Bit-exact: format conversions, Morton order.  FP64 factor: within c n u of the
+plain FP64 factor and of the KMS closed form.  Mixed factor: against the
+emulated mixed tile Cholesky with the factor-level gate
+||L_gpu - L_emu||_F / ||L_emu||_F <= 8 u_p sqrt(nt) on well-conditioned
+matrices.  Solves and log-likelihood: FP64 path |dl|/|l| <= 1e-12; mixed path
+refined to ||r||_2/||b||_2 <= 1e-9.
+"""
+import ctypes
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import covariance as cov  # noqa: E402
+from oracle import dense, fpformat as ff, loglik, tiled  # noqa: E402
+from tests.test_oracle_dense import kms, kms_loglik_closed_form  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests import gpu_util
+    ctx = gpu_util.Ctx()
+    yield gpu_util, ctx
+    ctx.close()
+
+
+def _factor_dense(gu, ctx, A, nb, m, expect_info=0):
+    from paper_2406_02701_amd import mpcr
+    n = A.shape[0]
+    dA = gu.dev(A)
+    hm = gu.u8map(m)
+    tm = mpcr.tilemap(n, nb, hm)
+    f = ctypes.c_void_p()
+    info = ctypes.c_int64(-1)
+    st = mpcr.mpcr_potrf_tiled(ctx.ptr, n, dA.data_ptr(), n, ctypes.byref(tm), ctypes.byref(f), ctypes.byref(info))
+    if expect_info:
+        assert st == mpcr.MPCR_ERR_NOT_SPD and info.value > 0
+    else:
+        ctx.check(st)
+        assert info.value == 0
+    return f, info.value
+
+
+def _to_dense(gu, ctx, f, n):
+    from paper_2406_02701_amd import mpcr
+    dL = gu.empty(n, n)
+    ctx.check(mpcr.mpcr_factor_to_dense(ctx.ptr, f, dL.data_ptr(), n))
+    return gu.host(dL, (n, n))
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8_e4m3"])
+def test_convert_bit_exact(g, fmt):
+    from paper_2406_02701_amd import mpcr
+    gu, ctx = g
+    rng = np.random.default_rng(1)
+    m, n = 300, 260
+    X = rng.standard_normal((m, n)) * np.exp(rng.uniform(-30, 12, (m, n)))
+    X[0, :8] = [1 + 2 ** -11, 1 + 3 * 2 ** -11, 1 + 2 ** -8, 65520.0, 1e-300, 0.0, -0.0, 2 ** -25]
+    X = np.asfortranarray(X)
+    f = ff.fmt_of(fmt)
+    width = {"fp32": np.float32, "fp16": np.uint16, "bf16": np.uint16, "fp8_e4m3": np.uint8}[fmt]
+    import torch as T
+    tdt = {"fp32": T.float32, "fp16": T.int16, "bf16": T.int16, "fp8_e4m3": T.uint8}[fmt]
+    dX = gu.dev(X)
+    dY = gu.empty(m, n, tdt)
+    scale = None
+    if f is ff.FP8_E4M3:
+        scale = T.zeros(((n + 127) // 128, (m + 127) // 128), dtype=T.int8, device="cuda")
+    ctx.check(mpcr.mpcr_convert(ctx.ptr, mpcr.PREC[fmt], m, n, dX.data_ptr(), m, dY.data_ptr(), m,
+                                None if scale is None else scale.data_ptr()))
+    Y = gu.host(dY, (m, n))
+    if f is ff.FP8_E4M3:
+        from oracle import gemm as og
+        Q, S = og.fp8_block_quantize(X)
+        assert np.array_equal(gu.host(scale, S.shape).astype(np.int64), S)
+        assert np.array_equal(Y.astype(np.uint64), ff.encode(Q, f))
+    elif fmt == "fp32":
+        assert np.array_equal(Y.astype(np.float64), ff.round_to(X, f))
+    else:
+        got = ff.decode(Y.astype(np.uint16).astype(np.uint64), f)
+        ref = ff.round_to(X, f)
+        assert np.array_equal(got, ref) or np.array_equal(np.nan_to_num(got), np.nan_to_num(ref))
+        assert np.array_equal(np.signbit(got), np.signbit(ref))
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 3000, 5000])
+def test_morton_order_bit_exact(g, n):
+    from paper_2406_02701_amd import mpcr
+    gu, ctx = g
+    locs = synth.locations(n, 70 + n)
+    if n >= 1000:
+        locs[10:20] = locs[5]                 # ties keep input order
+    dl = gu.dev(locs)
+    import torch as T
+    perm = T.zeros(n, dtype=T.int64, device="cuda")
+    ctx.check(mpcr.mpcr_morton_order(ctx.ptr, n, dl.data_ptr(), perm.data_ptr()))
+    assert np.array_equal(perm.cpu().numpy(), cov.morton_order(locs))
+
+
+def test_covariance_dense(g):
+    from paper_2406_02701_amd import mpcr
+    gu, ctx = g
+    n = 700
+    locs = synth.locations(n, 3)
+    for nu in (0.5, 1.5, 2.5):
+        th = gu.theta(1.3, 0.07, nu, 1e-5)
+        dA = gu.empty(n, n)
+        dl = gu.dev(locs)
+        ctx.check(mpcr.mpcr_covariance(ctx.ptr, n, dl.data_ptr(), ctypes.byref(th), dA.data_ptr(), n))
+        ref = cov.covariance(locs, 1.3, 0.07, nu, 1e-5)
+        np.testing.assert_allclose(gu.host(dA, (n, n)), ref, rtol=4e-15, atol=1e-300)
+
+
+@pytest.mark.parametrize("n,nb", [(500, 128), (512, 256), (1000, 128)])
+def test_fp64_factor_kms_closed_form(g, n, nb):
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    rho = 0.9
+    A = np.asfortranarray(kms(n, rho))
+    f, _ = _factor_dense(gu, ctx, A, nb, tiled.tilemap_uniform(n, nb))
+    L = _to_dense(gu, ctx, f, n)
+    i = np.arange(n)
+    ref = np.where(i[:, None] >= i[None, :], rho ** (i[:, None] - i[None, :]) * math.sqrt(1 - rho ** 2), 0.0)
+    ref[:, 0] = rho ** i
+    np.testing.assert_allclose(L, ref, rtol=0, atol=1e-13)
+    ld = ctypes.c_double()
+    ctx.check(mpcr.mpcr_factor_logdet(ctx.ptr, f, ctypes.byref(ld)))
+    assert abs(ld.value - (n - 1) * math.log(1 - rho ** 2)) <= 1e-12 * n
+    mpcr.mpcr_factor_destroy(f)
+
+
+@pytest.mark.parametrize("n,nb,nu", [(1000, 128, 1.5), (777, 256, 0.5), (1536, 512, 2.5)])
+def test_fp64_factor_matches_oracle(g, n, nb, nu):
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    locs = synth.locations(n, 80)
+    locs = locs[cov.morton_order(locs)]
+    S = np.asfortranarray(cov.covariance(locs, 1.0, 0.1, nu, 1e-4))
+    f, _ = _factor_dense(gu, ctx, S, nb, tiled.tilemap_uniform(n, nb))
+    L = _to_dense(gu, ctx, f, n)
+    Ld = np.linalg.cholesky(S)
+    # backward error at the rounding level; forward error scaled by cond(L)
+    assert np.linalg.norm(L @ L.T - S) / np.linalg.norm(S) <= 4 * n * 2.0 ** -53
+    assert np.linalg.norm(L - Ld) / np.linalg.norm(Ld) <= 4 * n * 2.0 ** -53 * np.linalg.cond(Ld)
+    ld = ctypes.c_double()
+    ctx.check(mpcr.mpcr_factor_logdet(ctx.ptr, f, ctypes.byref(ld)))
+    ref_ld = dense.logdet_from_cholesky(Ld)
+    assert abs(ld.value - ref_ld) <= 1e-11 * abs(ref_ld)
+    # solves
+    B = synth.normal_rhs(n, 3, 81)
+    dB = gu.dev(B)
+    dW, dX = gu.empty(n, 3), gu.empty(n, 3)
+    ctx.check(mpcr.mpcr_trsm_forward(ctx.ptr, f, 3, dB.data_ptr(), n, dW.data_ptr(), n))
+    W = gu.host(dW, (n, 3))
+    Wref = dense.forward_substitution(Ld, B)
+    np.testing.assert_allclose(W, Wref, rtol=1e-9, atol=1e-9 * np.abs(Wref).max())
+    ctx.check(mpcr.mpcr_potrs(ctx.ptr, f, 3, dB.data_ptr(), n, dX.data_ptr(), n, None, 0, None, None))
+    X = gu.host(dX, (n, 3))
+    Xref = dense.cholesky_solve(Ld, B)
+    np.testing.assert_allclose(X, Xref, rtol=1e-8, atol=1e-8 * np.abs(Xref).max())
+    mpcr.mpcr_factor_destroy(f)
+
+
+def test_not_spd_reports_global_column(g):
+    gu, ctx = g
+    n, nb = 700, 128
+    A = np.asfortranarray(kms(n, 0.5))
+    A[400, 400] = 0.3
+    f, info = _factor_dense(gu, ctx, A, nb, tiled.tilemap_uniform(n, nb), expect_info=True)
+    with pytest.raises(dense.NotPositiveDefinite) as e:
+        dense.cholesky_lower(A)
+    assert info == e.value.info
+    from paper_2406_02701_amd import mpcr
+    mpcr.mpcr_factor_destroy(f)
+
+
+@pytest.mark.parametrize("bands", [
+    ((1, "fp64"), (None, "fp32")),
+    ((1, "fp64"), (2, "fp32"), (None, "bf16")),
+    ((0, "fp64"), (1, "fp32"), (None, "fp16")),
+])
+def test_mixed_factor_matches_emulation(g, bands):
+    gu, ctx = g
+    n, nb, rho = 1000, 128, 0.5
+    A = np.asfortranarray(kms(n, rho))
+    m = tiled.tilemap_banded(n, nb, bands)
+    f, _ = _factor_dense(gu, ctx, A, nb, m)
+    L = _to_dense(gu, ctx, f, n)
+    emu = tiled.tile_cholesky_emulated(A, nb, m)["L"][:n, :n]
+    nt = m.shape[0]
+    up = max(ff.fmt_of(int(m[i, j])).unit_roundoff for i in range(nt) for j in range(i + 1))
+    err = np.linalg.norm(L - emu) / np.linalg.norm(emu)
+    assert err <= 8 * up * math.sqrt(nt), err
+    for i in range(nt):
+        for j in range(i + 1):
+            t = L[i * nb:min((i + 1) * nb, n), j * nb:min((j + 1) * nb, n)]
+            assert np.array_equal(ff.round_to(t, int(m[i, j])), t)
+    from paper_2406_02701_amd import mpcr
+    mpcr.mpcr_factor_destroy(f)
+
+
+def test_mixed_refined_solve_reaches_fp64(g):
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    n, nb = 1200, 128
+    locs = synth.locations(n, 90)
+    locs = locs[cov.morton_order(locs)]
+    S = np.asfortranarray(cov.covariance(locs, 1.0, 0.05, 1.5, 1e-6))
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (None, "fp32")))
+    f, _ = _factor_dense(gu, ctx, S, nb, m)
+    B = synth.normal_rhs(n, 4, 91)
+    dS, dB, dX = gu.dev(S), gu.dev(B), gu.empty(n, 4)
+    Xref = dense.cholesky_solve(np.linalg.cholesky(S), B)
+    sig_inf = np.max(np.sum(np.abs(S), axis=1))
+    for solver in (0, 1):
+        opts = mpcr.mpcr_refine_opts_t(1e-13, 100, solver, 20, 0)
+        diag = mpcr.mpcr_diag_t()
+        ctx.check(mpcr.mpcr_potrs(ctx.ptr, f, 4, dB.data_ptr(), n, dX.data_ptr(), n, dS.data_ptr(), n,
+                                  ctypes.byref(opts), ctypes.byref(diag)))
+        assert diag.converged == 1 and diag.eta <= 1e-13 and diag.iters >= 1
+        X = gu.host(dX, (n, 4))
+        R = B - S @ X
+        eta = np.max(np.abs(R), axis=0) / (sig_inf * np.max(np.abs(X), axis=0) + np.max(np.abs(B), axis=0))
+        assert np.max(eta) <= 2e-13
+        # same accuracy as the direct FP64 solve
+        np.testing.assert_allclose(X, Xref, rtol=0, atol=1e-6 * np.abs(Xref).max())
+    mpcr.mpcr_factor_destroy(f)
+
+
+def _loglik(gu, ctx, locs, Z, th, nb, m=None, order=1, opts=None):
+    from paper_2406_02701_amd import mpcr
+    n, nrhs = Z.shape
+    out = np.zeros(nrhs)
+    diag = mpcr.mpcr_diag_t()
+    hm = None if m is None else gu.u8map(m)
+    tm = None if m is None else ctypes.byref(mpcr.tilemap(n, nb, hm))
+    dl, dz = gu.dev(locs), gu.dev(Z)   # keep the device buffers alive across the call
+    st = mpcr.mpcr_gauss_loglik(ctx.ptr, n, dl.data_ptr(), dz.data_ptr(), nrhs,
+                                ctypes.byref(th), tm, order, None if opts is None else ctypes.byref(opts),
+                                mpcr.f64p(out), ctypes.byref(diag))
+    torch.cuda.synchronize()
+    del dl, dz
+    return st, out, diag
+
+
+def test_loglik_fp64_n1024_golden(g):
+    gu, ctx = g
+    gold = json.load(open(os.path.join(HERE, "golden", "fp64_n1024.json")))
+    w = synth.WORKLOADS["fp64_n1024"]
+    locs = synth.locations(w["n"], w["seed_locs"])
+    z = synth.normal_rhs(w["n"], 1, w["seed_z"])
+    th = gu.theta(w["sigma2"], w["range"], w["nu"], w["nugget"])
+    st, ll, diag = _loglik(gu, ctx, locs, z, th, w["nb"], tiled.tilemap_uniform(w["n"], w["nb"]))
+    ctx.check(st)
+    assert abs(ll[0] - gold["loglik"][0]) <= 1e-12 * abs(gold["loglik"][0])
+    assert abs(diag.logdet - gold["logdet"]) <= 1e-12 * abs(gold["logdet"])
+    assert diag.eta <= 1e-12
+
+
+@pytest.mark.parametrize("n,nb,bands", [
+    (4096, 256, None),
+    (4096, 256, ((1, "fp64"), (None, "fp32"))),
+    (3000, 128, ((2, "fp64"), (5, "fp32"), (None, "bf16"))),
+])
+def test_loglik_kms_closed_form(g, n, nb, bands):
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    h, a = 1.0 / n, 8.0 / n
+    locs = synth.grid_1d(n, h)
+    z = synth.normal_rhs(n, 2, 92)
+    th = gu.theta(1.0, a, 0.5, 0.0)
+    m = tiled.tilemap_uniform(n, nb) if bands is None else tiled.tilemap_banded(n, nb, bands)
+    opts = None if bands is None else mpcr.mpcr_refine_opts_t(1e-14, 100, 0, 20, 0)
+    st, ll, diag = _loglik(gu, ctx, locs, z, th, nb, m, order=0, opts=opts)
+    ctx.check(st)
+    rho = math.exp(-h / a)
+    for c in range(2):
+        logdet, q, ref = kms_loglik_closed_form(z[:, c], 1.0, rho)
+        tol = 1e-11 if bands is None else 1e-6
+        assert abs(ll[c] - ref) <= tol * abs(ref), (ll[c], ref)
+        if bands is None:
+            assert abs(diag.logdet - logdet) <= 1e-11 * abs(logdet)
+
+
+def test_loglik_mixed_matches_plain_oracle(g):
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    n, nb = 2048, 128
+    locs = synth.locations(n, 4)
+    z = synth.normal_rhs(n, 4, 5)
+    th = gu.theta(1.0, 0.05, 1.5, 1e-6)
+    lo, zo, _ = loglik.order_sites(locs, z)
+    ref = loglik.loglik_plain(lo, zo, 1.0, 0.05, 1.5, 1e-6)
+    m = tiled.tilemap_banded(n, nb, ((2, "fp64"), (None, "fp32")))
+    opts = mpcr.mpcr_refine_opts_t(1e-13, 100, 0, 20, 0)
+    st, ll, diag = _loglik(gu, ctx, locs, z, th, nb, m, order=1, opts=opts)
+    ctx.check(st)
+    assert diag.converged == 1 and diag.eta <= 1e-13
+    # quad is refined to FP64 accuracy; logdet carries the FP32 tiles' error
+    assert abs(diag.quad0 - ref["quad"][0]) <= 1e-8 * abs(ref["quad"][0])
+    assert abs(diag.logdet - ref["logdet"]) <= 1e-5 * abs(ref["logdet"])
+    # all-FP64 map through the same entry point.  This covariance has cond ~ 1e8,
+    # so the forward error of quad = ||L^{-1} z||^2 is ~ cond(L) n u ~ 1e-10: gate 1e-9
+    # (the well-conditioned 1024-site case is gated at 1e-12).
+    st, ll64, d64 = _loglik(gu, ctx, locs, z, th, nb, tiled.tilemap_uniform(n, nb), order=1)
+    ctx.check(st)
+    assert d64.eta <= 1e-12
+    np.testing.assert_allclose(ll64, ref["loglik"], rtol=1e-9)
+
+
+def test_literal_bf16_band_map_breaks_down(g):
+    """The BF16 far band on this ill-conditioned Matern 3/2 covariance makes the
+    stored matrix indefinite; the library must report NOT_SPD with a column."""
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    n, nb = 2048, 128
+    locs = synth.locations(n, 4)
+    z = synth.normal_rhs(n, 1, 5)
+    th = gu.theta(1.0, 0.05, 1.5, 1e-6)
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (4, "fp32"), (None, "bf16")))
+    st, ll, diag = _loglik(gu, ctx, locs, z, th, nb, m, order=1, opts=mpcr.mpcr_refine_opts_t(1e-9, 50, 0, 20, 0))
+    assert st == mpcr.MPCR_ERR_NOT_SPD
+    assert 1 <= diag.info <= n
