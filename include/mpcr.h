@@ -136,10 +136,13 @@ const char* mpcr_version(void);
  * launch queued by this context is bracketed by two HIP events recorded on the
  * context's stream; elapsed times are accumulated when the call synchronises.
  * Kinds: 0..4 = tile GEMM/SYRK update computed in format MPCR_FP64..FP8,
- * 5 = diagonal POTRF, 6 = panel TRSM.  mpcr_ctx_kernel_stats returns, for one
- * kind, the total milliseconds, the number of launches and the algorithmic
- * flops those launches performed (2 nb^3 per GEMM tile, nb^3 per SYRK tile,
- * nb^3 per TRSM tile, nb^3/3 per POTRF).  Reset clears all kinds. */
+ * 5 = diagonal POTRF, 6 = panel TRSM, 7 = inversion of the diagonal tiles,
+ * 8 = one tile solve (forward and backward sweeps, timed as a whole),
+ * 9 = FP64 residual b - Sigma x.  mpcr_ctx_kernel_stats returns, for one
+ * kind, the total milliseconds, the number of launches (sweeps for kind 8)
+ * and the algorithmic flops they performed (2 nb^3 per GEMM tile, nb^3 per
+ * SYRK or TRSM tile, nb^3/3 per POTRF or inversion, 2 N^2 nrhs per sweep,
+ * 2 n^2 nrhs per residual).  Reset clears all kinds. */
 int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on);
 int mpcr_ctx_reset_stats(mpcr_ctx* ctx);
 int mpcr_ctx_kernel_stats(const mpcr_ctx* ctx, int kind, double* h_total_ms, int64_t* h_launches,

@@ -16,6 +16,8 @@
 
 using namespace mpcr;
 
+constexpr int NKIND = 10;  // kernel kinds timed by the context (see mpcr_ctx_kernel_stats)
+
 struct mpcr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -33,8 +35,11 @@ struct mpcr_ctx {
   std::vector<hipEvent_t> ev_pool;
   struct Pending { hipEvent_t a, b; int kind; double flops; };
   std::vector<Pending> pending;
-  double k_ms[7] = {0}, k_flops[7] = {0};
-  int64_t k_launches[7] = {0};
+  double k_ms[NKIND] = {0}, k_flops[NKIND] = {0};
+  int64_t k_launches[NKIND] = {0};
+  // lookahead: a second stream for the bulk of each trailing update
+  hipStream_t upd = nullptr;
+  std::vector<hipEvent_t> sync_ev;  // timing-disabled events, 2 per step
 };
 
 namespace {
@@ -62,17 +67,31 @@ void drain_timing(mpcr_ctx* ctx) {
   }
   ctx->pending.clear();
 }
-// Runs `launch` between two events when profiling is on.
+// Runs `launch` (queued on stream s) between two events when profiling is on.
 template <class F>
-hipError_t timed(mpcr_ctx* ctx, int kind, double flops, F&& launch) {
+hipError_t timed(mpcr_ctx* ctx, hipStream_t s, int kind, double flops, F&& launch) {
   if (!ctx->profiling) return launch();
   hipEvent_t a = take_event(ctx), b = take_event(ctx);
   if (!a || !b) return launch();
-  hipError_t e = hipEventRecord(a, ctx->stream);
+  hipError_t e = hipEventRecord(a, s);
   if (e == hipSuccess) e = launch();
-  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
   ctx->pending.push_back({a, b, kind, flops});
   return e;
+}
+
+hipError_t ensure_lookahead(mpcr_ctx* ctx, size_t nev) {
+  if (!ctx->upd) {
+    hipError_t e = hipStreamCreateWithFlags(&ctx->upd, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  while (ctx->sync_ev.size() < nev) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    ctx->sync_ev.push_back(ev);
+  }
+  return hipSuccess;
 }
 }  // namespace
 
@@ -92,6 +111,7 @@ struct mpcr_factor {
   GemmTask* d_tasks = nullptr;
   std::vector<int64_t> task_off;   // [(k * 5 + f)] offset into d_tasks
   std::vector<int> task_cnt;
+  std::vector<int> task_cnt_next;  // leading tasks of each list that update column k+1
   double flops[5] = {0, 0, 0, 0, 0};
   int64_t info = 0;
 
@@ -109,16 +129,15 @@ struct mpcr_factor {
 };
 
 static const char* kVersion = "mpcr 0.1 gfx950";
+static thread_local std::string g_err;  // last error of calls made without a context
 
 static int set_err(mpcr_ctx* ctx, int code, const char* fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    ctx->err = buf;
-  }
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  (ctx ? ctx->err : g_err) = buf;
   return code;
 }
 
@@ -217,6 +236,7 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
   std::vector<GemmTask> tasks;
   f->task_off.assign(nt * 5, 0);
   f->task_cnt.assign(nt * 5, 0);
+  f->task_cnt_next.assign(nt * 5, 0);
   for (int64_t k = 0; k < nt; ++k) {
     f->flops[F64] += (double)nb * nb * nb / 3.0;
     for (int64_t i = k + 1; i < nt; ++i) f->flops[F64] += 2.0 * (double)nb * nb * nb;  // TRSM + SYRK
@@ -229,6 +249,9 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
             if (i != j) f->flops[p] += 2.0 * (double)nb * nb * nb;
           }
       f->task_cnt[k * 5 + p] = (int)((int64_t)tasks.size() - f->task_off[k * 5 + p]);
+      int nx = 0;
+      for (int64_t t = f->task_off[k * 5 + p]; t < (int64_t)tasks.size(); ++t) nx += (tasks[t].j == k + 1);
+      f->task_cnt_next[k * 5 + p] = nx;
     }
   }
   hipError_t e;
@@ -254,26 +277,51 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
 }
 
 // Queues the whole right-looking factorisation of an already filled tile store.
+// Queues the right-looking factorisation with a depth-1 lookahead.  The
+// context's stream P carries the critical path: POTRF(k), TRSM(k), then the
+// update of column k+1 (so POTRF(k+1) can start at once); the second stream U
+// carries the rest of step k's trailing update.  U waits for TRSM(k) before
+// its part of step k; P waits for U's step k-1 only before it updates column
+// k+1 in step k, so POTRF(k) and TRSM(k) overlap U's step k-1.
 int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
-  hipStream_t s = ctx->stream;
+  hipStream_t P = ctx->stream;
   TileView tv = f->view();
   f->linv_ready = false;
   const double nb3 = (double)f->nb * f->nb * f->nb;
-  for (int64_t k = 0; k < f->nt; ++k) {
-    HIP_TRY(ctx, timed(ctx, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, s); }));
-    HIP_TRY(ctx, timed(ctx, 6, nb3 * (double)(f->nt - k - 1),
-                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, s); }));
-    static const int order[4] = {F64, F32, BF16, F16};
+  const int64_t nt = f->nt;
+  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(2 * nt + 2)));
+  hipStream_t U = ctx->upd;
+  auto ev = [&](int64_t i) { return ctx->sync_ev[i]; };
+  // U starts after everything queued on P so far (the tile fill)
+  HIP_TRY(ctx, hipEventRecord(ev(2 * nt), P));
+  HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * nt), 0));
+  static const int order[4] = {F64, F32, BF16, F16};
+  auto launch_updates = [&](int64_t k, hipStream_t s, bool next_col) -> int {
     for (int p : order) {
-      int cnt = f->task_cnt[k * 5 + p];
+      const int all = f->task_cnt[k * 5 + p], nx = f->task_cnt_next[k * 5 + p];
+      const int cnt = next_col ? nx : all - nx;
       if (!cnt) continue;
-      double fl = 2.0 * nb3 * cnt;
-      if (p == F64) fl -= nb3 * (double)(f->nt - k - 1);  // the SYRK tasks count nb^3 each
-      HIP_TRY(ctx, timed(ctx, p, fl, [&] {
-        return launch_tile_update(tv, (int)k, p, f->d_tasks + f->task_off[k * 5 + p], cnt, s);
-      }));
+      const GemmTask* t = f->d_tasks + f->task_off[k * 5 + p] + (next_col ? 0 : nx);
+      // GEMM tiles count 2 nb^3, the SYRK (diagonal) tiles nb^3
+      const double ndiag = (p == F64) ? (next_col ? 1.0 : (double)(nt - k - 2)) : 0.0;
+      const double fl = nb3 * (2.0 * cnt - ndiag);
+      HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s); }));
     }
+    return MPCR_OK;
+  };
+  int rc;
+  for (int64_t k = 0; k < nt; ++k) {
+    HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, P); }));
+    HIP_TRY(ctx, timed(ctx, P, 6, nb3 * (double)(nt - k - 1),
+                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, P); }));
+    HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
+    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
+    if ((rc = launch_updates(k, P, true)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * k), 0));
+    if ((rc = launch_updates(k, U, false)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, hipEventRecord(ev(2 * k + 1), U));
   }
+  HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * nt - 1), 0));  // join
   return MPCR_OK;
 }
 
@@ -291,7 +339,9 @@ int read_info(mpcr_ctx* ctx, mpcr_factor* f, int64_t* h_info) {
 int ensure_linv(mpcr_ctx* ctx, mpcr_factor* f) {
   if (f->linv_ready) return MPCR_OK;
   if (!f->d_Linv) HIP_TRY(ctx, dmalloc(&f->d_Linv, (size_t)2 * f->nt * f->nb * f->nb * 8));
-  HIP_TRY(ctx, launch_trtri_diag(f->view(), f->d_Linv, ctx->stream));
+  const double nb3 = (double)f->nb * f->nb * f->nb;
+  HIP_TRY(ctx, timed(ctx, ctx->stream, 7, nb3 / 3.0 * (double)f->nt,
+                     [&] { return launch_trtri_diag(f->view(), f->d_Linv, ctx->stream); }));
   f->linv_ready = true;
   return MPCR_OK;
 }
@@ -347,31 +397,41 @@ int tile_solve(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const double* Bsrc, 
   TileView tv = f->view();
   const int nrhs = (int)b.nrhs;
   const int64_t ld = b.N;
-  // b.V is the working copy of both sweeps, so Bsrc may be any other block
-  HIP_TRY(ctx, launch_copy_cols((int)f->N, nrhs, Bsrc, ld, b.V, ld, s));
-  for (int64_t k = 0; k < f->nt; ++k) {
-    HIP_TRY(ctx, launch_fwd_diag(tv, f->d_Linv, (int)k, b.V, Wdst, ld, nrhs, s));
-    HIP_TRY(ctx, launch_fwd_update(tv, (int)k, b.V, Wdst, ld, nrhs, s));
-  }
-  if (!backward) return MPCR_OK;
-  HIP_TRY(ctx, launch_copy_cols((int)f->N, nrhs, Wdst, ld, b.V, ld, s));
-  for (int64_t k = f->nt - 1; k >= 0; --k) {
-    HIP_TRY(ctx, launch_bwd_diag(tv, f->d_Linv, (int)k, b.V, Xdst, ld, nrhs, s));
-    HIP_TRY(ctx, launch_bwd_update(tv, (int)k, b.V, Xdst, ld, nrhs, s));
-  }
+  // algorithmic flops: 2 N^2 nrhs per triangular sweep
+  const double fl = 2.0 * (double)f->N * (double)f->N * nrhs * (backward ? 2.0 : 1.0);
+  hipError_t e = timed(ctx, s, 8, fl, [&]() -> hipError_t {
+    // b.V is the working copy of both sweeps, so Bsrc may be any other block
+    hipError_t r = launch_copy_cols((int)f->N, nrhs, Bsrc, ld, b.V, ld, s);
+    for (int64_t k = 0; k < f->nt && r == hipSuccess; ++k) {
+      r = launch_fwd_diag(tv, f->d_Linv, (int)k, b.V, Wdst, ld, nrhs, s);
+      if (r == hipSuccess) r = launch_fwd_update(tv, (int)k, b.V, Wdst, ld, nrhs, s);
+    }
+    if (!backward || r != hipSuccess) return r;
+    r = launch_copy_cols((int)f->N, nrhs, Wdst, ld, b.V, ld, s);
+    for (int64_t k = f->nt - 1; k >= 0 && r == hipSuccess; --k) {
+      r = launch_bwd_diag(tv, f->d_Linv, (int)k, b.V, Xdst, ld, nrhs, s);
+      if (r == hipSuccess) r = launch_bwd_update(tv, (int)k, b.V, Xdst, ld, nrhs, s);
+    }
+    return r;
+  });
+  HIP_TRY(ctx, e);
   return MPCR_OK;
 }
 
 // Sigma application for refinement: either matrix-free from sites or a dense FP64 matrix.
 struct SigmaOp {
+  mpcr_ctx* ctx = nullptr;  // for kernel timing
   const double* locs = nullptr;
   mpcr_theta_t th{};
   const double* A = nullptr;
   int64_t lda = 0;
   int n = 0;
   hipError_t residual(const double* B, const double* X, double* R, int64_t ld, int nrhs, hipStream_t s) const {
-    return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s)
-             : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s);
+    auto go = [&] {
+      return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s)
+               : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s);
+    };
+    return ctx ? timed(ctx, s, 9, 2.0 * (double)n * n * nrhs, go) : go();
   }
   hipError_t rowsum(double* out, hipStream_t s) const {
     return A ? launch_rowsum_abs_dense(n, A, lda, out, s) : launch_rowsum_abs_cov(n, locs, th, out, s);
@@ -421,7 +481,7 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
   }
   if ((rc = push_active()) != MPCR_OK) return rc;
   int it = 0;
-  if (o.solver == 0) {
+  if (o.solver == 0 && nact > 0) {
     if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;  // z = M^{-1} r
     HIP_TRY(ctx, launch_copy_cols((int)b.N, nrhs, b.Z, ld, b.P, ld, s));
     HIP_TRY(ctx, launch_col_dot(n, nrhs, b.R, b.Z, ld, b.partial, rz, s));
@@ -511,19 +571,21 @@ extern "C" {
 const char* mpcr_version(void) { return kVersion; }
 
 int mpcr_ctx_create(int device, void* hip_stream, mpcr_ctx** out) {
-  if (!out) return MPCR_ERR_ARG;
+  if (!out) return set_err(nullptr, MPCR_ERR_ARG, "out is NULL");
   *out = nullptr;
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return MPCR_ERR_DEVICE;
-  if (device < 0 || device >= ndev) return MPCR_ERR_ARG;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0)
+    return set_err(nullptr, MPCR_ERR_DEVICE, "hipGetDeviceCount: %s (%d devices)", hipGetErrorString(e), ndev);
+  if (device < 0 || device >= ndev) return set_err(nullptr, MPCR_ERR_ARG, "device %d out of range", device);
   auto* c = new mpcr_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   DeviceGuard g(device);
-  for (auto& e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
+  for (auto& ev : c->ev)
+    if ((e = hipEventCreate(&ev)) != hipSuccess) {
       delete c;
-      return MPCR_ERR_DEVICE;
+      return set_err(nullptr, MPCR_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
     }
   *out = c;
   return MPCR_OK;
@@ -540,12 +602,14 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     drain_timing(ctx);
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto& e : ctx->sync_ev) (void)hipEventDestroy(e);
+    if (ctx->upd) (void)hipStreamDestroy(ctx->upd);
   }
   delete ctx;
   return MPCR_OK;
 }
 
-const char* mpcr_last_error(const mpcr_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+const char* mpcr_last_error(const mpcr_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
 int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on) {
   if (!ctx) return MPCR_ERR_ARG;
@@ -555,7 +619,7 @@ int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on) {
 
 int mpcr_ctx_reset_stats(mpcr_ctx* ctx) {
   if (!ctx) return MPCR_ERR_ARG;
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < NKIND; ++k) {
     ctx->k_ms[k] = 0;
     ctx->k_flops[k] = 0;
     ctx->k_launches[k] = 0;
@@ -564,7 +628,7 @@ int mpcr_ctx_reset_stats(mpcr_ctx* ctx) {
 }
 
 int mpcr_ctx_kernel_stats(const mpcr_ctx* ctx, int kind, double* h_total_ms, int64_t* h_launches, double* h_flops) {
-  if (!ctx || kind < 0 || kind > 6) return MPCR_ERR_ARG;
+  if (!ctx || kind < 0 || kind >= NKIND) return MPCR_ERR_ARG;
   if (h_total_ms) *h_total_ms = ctx->k_ms[kind];
   if (h_launches) *h_launches = ctx->k_launches[kind];
   if (h_flops) *h_flops = ctx->k_flops[kind];
@@ -806,6 +870,7 @@ int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double*
   bool conv = true;
   if (do_ref) {
     SigmaOp op;
+    op.ctx = ctx;
     op.A = d_A_fp64;
     op.lda = lda;
     op.n = (int)f->n;
@@ -816,6 +881,7 @@ int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double*
   }
   HIP_TRY(ctx, launch_copy_cols((int)f->n, (int)nrhs, b.X, b.N, d_X, ldx, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  drain_timing(ctx);
   if (diag) diag->info = 0;
   if (!conv) return set_err(ctx, MPCR_ERR_NOT_CONVERGED, "refinement did not reach the tolerance");
   return MPCR_OK;
@@ -927,6 +993,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     HIP_TRY(ctx, hipEventRecord(ctx->ev[4], s));
     if (diag) {  // report the backward error of the direct solve
       SigmaOp op;
+      op.ctx = ctx;
       op.locs = locs;
       op.th = *theta;
       op.n = (int)n;
@@ -948,6 +1015,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   } else {
     mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0};
     SigmaOp op;
+    op.ctx = ctx;
     op.locs = locs;
     op.th = *theta;
     op.n = (int)n;
@@ -967,6 +1035,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   HIP_TRY(ctx, hipMemcpyAsync(&host_ld, d_logdet, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipMemcpyAsync(&host_q0, d_quad, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  drain_timing(ctx);
   if (diag) {
     diag->logdet = host_ld;
     diag->quad0 = host_q0;

@@ -10,6 +10,8 @@
 //   GEMM   A_ij -= L_ik L_jk^T (i > j)                MFMA in the format of tile (i,j)
 // Every kernel first checks the device info word and does nothing once a
 // pivot has failed, so a whole factorisation can be queued without host syncs.
+#include <type_traits>
+
 #include "mpcr_internal.h"
 
 namespace mpcr {
@@ -59,16 +61,53 @@ __device__ __forceinline__ typename CTraits<CF>::T load_as(const void* p, int f,
 // ---------------------------------------------------------------------------
 constexpr int UBM = 128;
 
-// FP64 / FP32: operands staged k-major in LDS ([k][m]); fragments are
-// contiguous across lanes.
+// Four consecutive elements (idx % 4 == 0) of a tile stored in format SF,
+// converted to the compute type of CF with one vector load.
+template <int CF, int SF>
+__device__ __forceinline__ void load4(const void* p, int64_t idx, typename CTraits<CF>::T out[4]) {
+  using T = typename CTraits<CF>::T;
+  if constexpr (SF == F64) {
+    const double4 v = *(const double4*)((const double*)p + idx);
+    const double w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = (CF == F64) ? (T)w[r] : (T)to_f32(w[r]);
+  } else if constexpr (SF == F32) {
+    const float4 v = *(const float4*)((const float*)p + idx);
+    out[0] = (T)v.x; out[1] = (T)v.y; out[2] = (T)v.z; out[3] = (T)v.w;
+  } else if constexpr (SF == F16 || SF == BF16) {
+    const ushort4 v = *(const ushort4*)((const uint16_t*)p + idx);
+    const uint16_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = (T)(SF == F16 ? f16_to_f32(w[r]) : bf16_to_f32(w[r]));
+  } else {
+    const uchar4 v = *(const uchar4*)((const uint8_t*)p + idx);
+    const uint8_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = (T)e4m3_to_f32(w[r]);
+  }
+}
+
+// C[idx] <- round_f(C[idx] - acc) for the epilogue, with a static format.
+template <int F>
+__device__ __forceinline__ void rmw_sub(void* Cp, int64_t idx, double acc) {
+  if constexpr (F == F64) { double* c = (double*)Cp; c[idx] = c[idx] - acc; }
+  else if constexpr (F == F32) { float* c = (float*)Cp; c[idx] = to_f32((double)c[idx] - acc); }
+  else if constexpr (F == F16) { uint16_t* c = (uint16_t*)Cp; c[idx] = to_f16((double)f16_to_f32(c[idx]) - acc); }
+  else if constexpr (F == BF16) { uint16_t* c = (uint16_t*)Cp; c[idx] = to_bf16((double)bf16_to_f32(c[idx]) - acc); }
+  else { uint8_t* c = (uint8_t*)Cp; c[idx] = to_e4m3((double)e4m3_to_f32(c[idx]) - acc); }
+}
+
+// FP64 / FP32: operands staged k-major in LDS ([k][m]), double-buffered;
+// fragments are contiguous across lanes.  The source format of each operand is
+// dispatched once per k chunk, not per element.
 template <int CF>
 __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
   using T = typename CTraits<CF>::T;
   constexpr int BK = (CF == F64) ? 16 : 32;
   constexpr int PAD = (CF == F64) ? 2 : 4;
   constexpr int G = BK / 8;  // 4-row groups per thread per operand
-  __shared__ __attribute__((aligned(16))) T As[BK][UBM + PAD];
-  __shared__ __attribute__((aligned(16))) T Bs[BK][UBM + PAD];
+  __shared__ __attribute__((aligned(16))) T As[2][BK][UBM + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BK][UBM + PAD];
 
   const int nb = tv.nb;
   const int sub = nb / UBM;
@@ -89,24 +128,28 @@ __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const
   const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
 
   T ra[G][4], rb[G][4];
-  auto gload = [&](int kk) {
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      int64_t col = kk + lc + 8 * g;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        ra[g][r] = load_as<CF>(Ap, fa, col * nb + arow0 + lr + r);
-        rb[g][r] = load_as<CF>(Bp, fb, col * nb + brow0 + lr + r);
-      }
+  auto gload_op = [&](const void* P, int f, int64_t row0, int kk, T (*dst)[4]) {
+#define MPCR_LOAD_CASE(SF)                                                    \
+  case SF:                                                                    \
+    _Pragma("unroll") for (int g = 0; g < G; ++g)                             \
+      load4<CF, SF>(P, (int64_t)(kk + lc + 8 * g) * nb + row0 + lr, dst[g]);  \
+    break;
+    switch (f) {
+      MPCR_LOAD_CASE(F64)
+      MPCR_LOAD_CASE(F32)
+      MPCR_LOAD_CASE(F16)
+      MPCR_LOAD_CASE(BF16)
+      MPCR_LOAD_CASE(F8)
     }
+#undef MPCR_LOAD_CASE
   };
-  auto sstore = [&]() {
+  auto sstore = [&](int buf) {
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        As[lc + 8 * g][lr + r] = ra[g][r];
-        Bs[lc + 8 * g][lr + r] = rb[g][r];
+        As[buf][lc + 8 * g][lr + r] = ra[g][r];
+        Bs[buf][lc + 8 * g][lr + r] = rb[g][r];
       }
   };
 
@@ -117,19 +160,24 @@ __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  gload(0);
+  gload_op(Ap, fa, arow0, 0, ra);
+  gload_op(Bp, fb, brow0, 0, rb);
+  sstore(0);
+  __syncthreads();
+  int cur = 0;
   for (int kk = 0; kk < nb; kk += BK) {
-    __syncthreads();
-    sstore();
-    __syncthreads();
-    if (kk + BK < nb) gload(kk + BK);
+    const bool more = kk + BK < nb;
+    if (more) {
+      gload_op(Ap, fa, arow0, kk + BK, ra);
+      gload_op(Bp, fb, brow0, kk + BK, rb);
+    }
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
       T av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[k4 + (lane >> 4)][wm * 64 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 4; ++a) av[a] = As[cur][k4 + (lane >> 4)][wm * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[k4 + (lane >> 4)][wn * 64 + b * 16 + (lane & 15)];
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[cur][k4 + (lane >> 4)][wn * 64 + b * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -140,25 +188,36 @@ __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
     }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
   }
 
   void* Cp = tv.tile(t.i, t.j);
   const int fc = tv.tfmt(t.i, t.j);
   const bool diag = (t.i == t.j);
+  auto epilogue = [&](auto fmt_tag) {
+    constexpr int FC = decltype(fmt_tag)::value;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row = (CF == F64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
-        int64_t R = arow0 + wm * 64 + a * 16 + row;
-        int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
-        if (diag && C > R) continue;
-        int64_t idx = C * nb + R;
-        double c = load_wide(Cp, fc, idx) - (double)acc[a][b][r];
-        store_round(Cp, fc, idx, c);
-      }
+        for (int r = 0; r < 4; ++r) {
+          int row = (CF == F64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
+          int64_t R = arow0 + wm * 64 + a * 16 + row;
+          int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
+          if (diag && C > R) continue;
+          rmw_sub<FC>(Cp, C * nb + R, (double)acc[a][b][r]);
+        }
+  };
+  switch (fc) {
+    case F64: epilogue(std::integral_constant<int, F64>{}); break;
+    case F32: epilogue(std::integral_constant<int, F32>{}); break;
+    case F16: epilogue(std::integral_constant<int, F16>{}); break;
+    case BF16: epilogue(std::integral_constant<int, BF16>{}); break;
+    default: epilogue(std::integral_constant<int, F8>{}); break;
+  }
 }
 
 // BF16 / FP16: operands staged m-major in LDS ([m][k]) so that each lane reads
@@ -278,32 +337,57 @@ hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTas
 // block in LDS, (3) the rows below solved against it by substitution.
 // ---------------------------------------------------------------------------
 constexpr int PW = 32;
+constexpr int POTRF_THREADS = 512;
 
-__global__ __launch_bounds__(256) void k_potrf(TileView tv, int k) {
+// acc0/acc1 (16 x 16 each) += A[R0.., 0:K] * B[C0.., 0:K]^T, operands read
+// straight from column-major FP64 storage (lda = ldb = ld), 16 k values per
+// batch so that twelve loads are in flight before the eight MFMAs use them.
+__device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B, int64_t ld, int R0, int C0, int K,
+                                               int lane, d4& acc0, d4& acc1) {
+  const int r = lane & 15, q = lane >> 4;
+  int kk = 0;
+  for (; kk + 16 <= K; kk += 16) {
+    double a[4], b0[4], b1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t col = kk + 4 * u + q;
+      a[u] = A[col * ld + R0 + r];
+      b0[u] = B[col * ld + C0 + r];
+      b1[u] = B[col * ld + C0 + 16 + r];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b0[u], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b1[u], acc1, 0, 0, 0);
+    }
+  }
+  for (; kk < K; kk += 4) {
+    const int64_t col = kk + q;
+    double a = A[col * ld + R0 + r], b0 = B[col * ld + C0 + r], b1 = B[col * ld + C0 + 16 + r];
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(POTRF_THREADS) void k_potrf(TileView tv, int k) {
   if (*tv.info) return;
   const int nb = tv.nb;
   double* A = (double*)tv.tile(k, k);
   __shared__ double D[PW][PW + 1];
-  __shared__ double Xs[256][PW + 1];
+  __shared__ double Xs[POTRF_THREADS][PW + 1];
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = POTRF_THREADS / 64;
   if (tid == 0) fail = 0;
 
   for (int J0 = 0; J0 < nb; J0 += PW) {
     // (1) panel update with the columns already factored
     if (J0 > 0) {
       const int nrb = (nb - J0) / 16;  // 16-row blocks from J0 down
-      for (int rb = wave; rb < nrb; rb += 4) {
+      for (int rb = wave; rb < nrb; rb += NW) {
         const int R0 = J0 + rb * 16;
         d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        for (int kk = 0; kk < J0; kk += 4) {
-          const int64_t col = kk + (lane >> 4);
-          double a = A[col * nb + R0 + (lane & 15)];
-          double b0 = A[col * nb + J0 + (lane & 15)];
-          double b1 = A[col * nb + J0 + 16 + (lane & 15)];
-          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
-        }
+        mfma_rows16x32(A, A, nb, R0, J0, J0, lane, acc0, acc1);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int R = R0 + (lane >> 4) + 4 * r;
@@ -314,8 +398,8 @@ __global__ __launch_bounds__(256) void k_potrf(TileView tv, int k) {
       }
     }
     __syncthreads();
-    // (2) diagonal 32 x 32 block
-    for (int e = tid; e < PW * PW; e += 256) {
+    // (2) unblocked Cholesky of the 32 x 32 diagonal block in LDS
+    for (int e = tid; e < PW * PW; e += POTRF_THREADS) {
       int r = e % PW, c = e / PW;
       D[r][c] = (r >= c) ? A[(int64_t)(J0 + c) * nb + J0 + r] : 0.0;
     }
@@ -334,40 +418,38 @@ __global__ __launch_bounds__(256) void k_potrf(TileView tv, int k) {
       const double piv = D[c][c];
       if (tid > c && tid < PW) D[tid][c] /= piv;
       __syncthreads();
-      for (int e = tid; e < PW * PW; e += 256) {
+      for (int e = tid; e < PW * PW; e += POTRF_THREADS) {
         int r = e % PW, q = e / PW;
         if (q > c && r >= q) D[r][q] -= D[r][c] * D[q][c];
       }
       __syncthreads();
     }
-    for (int e = tid; e < PW * PW; e += 256) {
+    for (int e = tid; e < PW * PW; e += POTRF_THREADS) {
       int r = e % PW, c = e / PW;
       if (r >= c) A[(int64_t)(J0 + c) * nb + J0 + r] = D[r][c];
     }
     // (3) rows below: x L_JJ^T = a, one row per thread, the row kept in LDS
-    for (int R0 = J0 + PW; R0 < nb; R0 += 256) {
-      const int R = R0 + tid;
-      if (R < nb) {
-        for (int c = 0; c < PW; ++c) Xs[tid][c] = A[(int64_t)(J0 + c) * nb + R];
-        for (int c = 0; c < PW; ++c) {
-          double v = Xs[tid][c];
-          for (int m = 0; m < c; ++m) v -= Xs[tid][m] * D[c][m];
-          Xs[tid][c] = v / D[c][c];
-        }
-        for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + R] = Xs[tid][c];
+    for (int R = J0 + PW + tid; R < nb; R += POTRF_THREADS) {
+      double* x = Xs[tid];
+      for (int c = 0; c < PW; ++c) x[c] = A[(int64_t)(J0 + c) * nb + R];
+      for (int c = 0; c < PW; ++c) {
+        double v = x[c];
+        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
+        x[c] = v / D[c][c];
       }
+      for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + R] = x[c];
     }
     __syncthreads();
   }
   // zero the strictly upper triangle so the stored tile is exactly L_kk
-  for (int64_t e = tid; e < (int64_t)nb * nb; e += 256) {
+  for (int64_t e = tid; e < (int64_t)nb * nb; e += POTRF_THREADS) {
     int r = (int)(e % nb), c = (int)(e / nb);
     if (r < c) A[e] = 0.0;
   }
 }
 
 hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
-  k_potrf<<<1, 256, 0, s>>>(tv, k);
+  k_potrf<<<1, POTRF_THREADS, 0, s>>>(tv, k);
   return hipGetLastError();
 }
 
@@ -393,15 +475,7 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
   for (int J0 = 0; J0 < nb; J0 += PW) {
     // T = A[rows, J] - X[rows, :J0] L[J, :J0]^T ; wave w owns rows 16w .. 16w+15
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    const int R0 = r0 + wave * 16;
-    for (int kk = 0; kk < J0; kk += 4) {
-      const int64_t col = kk + (lane >> 4);
-      double a = X[col * nb + R0 + (lane & 15)];
-      double b0 = Lkk[col * nb + J0 + (lane & 15)];
-      double b1 = Lkk[col * nb + J0 + 16 + (lane & 15)];
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
-    }
+    mfma_rows16x32(X, Lkk, nb, r0 + wave * 16, J0, J0, lane, acc0, acc1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int lr = wave * 16 + (lane >> 4) + 4 * r;

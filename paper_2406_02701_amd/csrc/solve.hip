@@ -13,146 +13,214 @@
 namespace mpcr {
 
 constexpr int RHS_CHUNK = 16;
+constexpr int GROWS = 64;    // output rows per workgroup
+constexpr int GSPLIT = 4;    // k-split of the 256 threads (64 rows x 4)
 
-// out[r0 .. r0+63][c] (op) M[rows][0..nb) * V[0..nb)[c], M an nb x nb column-major
-// tile of format f.  mode 0: out = M V ; mode 1: out -= M V.  Thread (r, cq)
-// handles row r and columns cq, cq+4, cq+8, cq+12 of each 16-column chunk.
-__device__ void tile_gemv_n(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
-                            int64_t ldo, int nrhs, int mode, double* Vs /* LDS nb_chunk x 16 */) {
-  const int tid = threadIdx.x, r = tid & 63, cq = tid >> 6;
-  constexpr int KC = 256;
+template <int F>
+__device__ __forceinline__ double ldw(const void* p, int64_t i) {
+  if constexpr (F == F64) return ((const double*)p)[i];
+  else if constexpr (F == F32) return (double)((const float*)p)[i];
+  else if constexpr (F == F16) return (double)f16_to_f32(((const uint16_t*)p)[i]);
+  else if constexpr (F == BF16) return (double)bf16_to_f32(((const uint16_t*)p)[i]);
+  else return (double)e4m3_to_f32(((const uint8_t*)p)[i]);
+}
+
+// out[r0 .. r0+63][c] (op) M[r0 .. r0+63][0 .. nb) V[0 .. nb)[c] for one nb x nb
+// column-major tile M.  Thread (r, h) handles row r over the k-quarter h with
+// sixteen right-hand sides in registers; V is staged in LDS (k-major, 16
+// values per k, read as broadcasts); the four quarters are added in a fixed
+// order.  mode 0: out = M V, mode 1: out -= M V.
+template <int F>
+__device__ void gemv_n_rows(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
+                            int nrhs, int mode, double* Vs /* nb x 16 */) {
+  const int tid = threadIdx.x, r = tid & 63, h = tid >> 6;
+  double* part = Vs;  // 256 x 17 partial sums, written once the products are done
+  const int kq = nb / GSPLIT, kb = h * kq;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
-    double acc[4] = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < nb; k0 += KC) {
-      const int kc = (nb - k0) < KC ? (nb - k0) : KC;
-      __syncthreads();
-      for (int e = tid; e < KC * RHS_CHUNK; e += 256) {
-        int kk = e % KC, c = e / KC;
-        Vs[c * KC + kk] = (kk < kc && c0 + c < nrhs) ? V[(int64_t)(c0 + c) * ldv + k0 + kk] : 0.0;
-      }
-      __syncthreads();
-      for (int kk = 0; kk < kc; ++kk) {
-        double m = load_wide(M, f, (int64_t)(k0 + kk) * nb + r0 + r);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += m * Vs[(cq + 4 * q) * KC + kk];
-      }
+    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
+    __syncthreads();
+    for (int e = tid; e < nb * RHS_CHUNK; e += 256) {
+      const int c = e / nb, k = e % nb;
+      Vs[k * RHS_CHUNK + c] = c < nc ? V[(int64_t)(c0 + c) * ldv + k] : 0.0;
     }
+    __syncthreads();
+    double acc[RHS_CHUNK];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int c = c0 + cq + 4 * q;
-      if (c < nrhs) {
-        double* o = out + (int64_t)c * ldo + r0 + r;
-        *o = mode == 0 ? acc[q] : *o - acc[q];
+    for (int j = 0; j < RHS_CHUNK; ++j) acc[j] = 0.0;
+    const int64_t base = (int64_t)r0 + r;
+#pragma unroll 4
+    for (int k = kb; k < kb + kq; ++k) {
+      const double m = ldw<F>(M, (int64_t)k * nb + base);
+      const double* vk = Vs + k * RHS_CHUNK;
+#pragma unroll
+      for (int j = 0; j < RHS_CHUNK; ++j) acc[j] += m * vk[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RHS_CHUNK; ++j) part[tid * (RHS_CHUNK + 1) + j] = acc[j];
+    __syncthreads();
+    for (int e = tid; e < GROWS * RHS_CHUNK; e += 256) {
+      const int rr = e % GROWS, j = e / GROWS;
+      if (j < nc) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < GSPLIT; ++q) sum += part[(q * 64 + rr) * (RHS_CHUNK + 1) + j];
+        double* o = out + (int64_t)(c0 + j) * ldo + r0 + rr;
+        *o = mode == 0 ? sum : *o - sum;
       }
     }
   }
 }
 
-// out[r0 .. r0+63][c] (op) M^T[rows][...] V.  Thread (r, part) walks column r0+r of M
-// with stride 4 in k (4 consecutive threads read 32 consecutive bytes); the four
-// partial sums are combined in a fixed order through LDS.
-__device__ void tile_gemv_t(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
-                            int64_t ldo, int nrhs, int mode, double* Vs, double* part /* LDS 256 x 16 */) {
-  const int tid = threadIdx.x, r = tid >> 2, p = tid & 3;
-  constexpr int KC = 256;
+// out[r0 .. r0+63][c] (op) sum_k M[k][r] V[k][c]: the transposed product.  The
+// columns r0 .. r0+63 of M are one contiguous block; it is staged through LDS in
+// 64 x 64 pieces (each thread loads 16 consecutive elements of one column).
+template <int F>
+__device__ void gemv_t_rows(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
+                            int nrhs, int mode, double* lds) {
+  double* Vc = lds;            // 64 x 16: the piece of V
+  double* S = lds + 64 * 16;   // 64 x 65: the piece of M, S[r][k] = M[k0 + k][r0 + r]
+  const int tid = threadIdx.x;
+  const int rr = tid & 63, q = tid >> 6;         // compute: row rr, right-hand sides 4q .. 4q+3
+  const int lr = tid >> 2, lc = (tid & 3) * 16;  // load: column r0+lr of M, rows lc .. lc+15 of the piece
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
-    double acc[RHS_CHUNK];
-#pragma unroll
-    for (int q = 0; q < RHS_CHUNK; ++q) acc[q] = 0.0;
-    for (int k0 = 0; k0 < nb; k0 += KC) {
-      const int kc = (nb - k0) < KC ? (nb - k0) : KC;
+    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
+    double acc[4] = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < nb; k0 += 64) {
       __syncthreads();
-      for (int e = tid; e < KC * RHS_CHUNK; e += 256) {
-        int kk = e % KC, c = e / KC;
-        Vs[kk * RHS_CHUNK + c] = (kk < kc && c0 + c < nrhs) ? V[(int64_t)(c0 + c) * ldv + k0 + kk] : 0.0;
+      for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
+        const int c = e / 64, k = e % 64;
+        Vc[k * RHS_CHUNK + c] = c < nc ? V[(int64_t)(c0 + c) * ldv + k0 + k] : 0.0;
       }
-      __syncthreads();
-      for (int kk = p; kk < kc; kk += 4) {
-        double m = load_wide(M, f, (int64_t)(r0 + r) * nb + k0 + kk);
+      const int64_t src = (int64_t)(r0 + lr) * nb + k0 + lc;
 #pragma unroll
-        for (int q = 0; q < RHS_CHUNK; ++q) acc[q] += m * Vs[kk * RHS_CHUNK + q];
+      for (int e = 0; e < 16; ++e) S[lr * 65 + lc + e] = ldw<F>(M, src + e);
+      __syncthreads();
+#pragma unroll 8
+      for (int k = 0; k < 64; ++k) {
+        const double m = S[rr * 65 + k];
+        const double* vk = Vc + k * RHS_CHUNK + 4 * q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += m * vk[j];
       }
     }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < RHS_CHUNK; ++q) part[tid * RHS_CHUNK + q] = acc[q];
-    __syncthreads();
-    for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
-      int rr = e % 64, q = e / 64;
-      int c = c0 + q;
-      if (c < nrhs) {
-        const double* ps = part + (rr * 4) * RHS_CHUNK + q;
-        double s = ((ps[0] + ps[RHS_CHUNK]) + ps[2 * RHS_CHUNK]) + ps[3 * RHS_CHUNK];
-        double* o = out + (int64_t)c * ldo + r0 + rr;
-        *o = mode == 0 ? s : *o - s;
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * q + j;
+      if (c < nc) {
+        double* o = out + (int64_t)(c0 + c) * ldo + r0 + rr;
+        *o = mode == 0 ? acc[j] : *o - acc[j];
       }
     }
   }
+}
+
+template <bool TRANS>
+__device__ void tile_gemv(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
+                          int64_t ldo, int nrhs, int mode, double* lds) {
+#define MPCR_GEMV_CASE(FMT)                                                                   \
+  case FMT:                                                                                  \
+    if (TRANS) gemv_t_rows<FMT>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);               \
+    else gemv_n_rows<FMT>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);                     \
+    break;
+  switch (f) {
+    MPCR_GEMV_CASE(F64)
+    MPCR_GEMV_CASE(F32)
+    MPCR_GEMV_CASE(F16)
+    MPCR_GEMV_CASE(BF16)
+    MPCR_GEMV_CASE(F8)
+  }
+#undef MPCR_GEMV_CASE
+}
+
+// dynamic LDS: the N product stages V for a whole tile (nb x 16 doubles, 128 KiB
+// at nb = 1024) and reuses it for the partial sums; the T product needs 64 x 16
+// + 64 x 65 doubles.
+static size_t gemv_lds(int nb) {
+  size_t n = (size_t)nb * RHS_CHUNK, t = 64 * RHS_CHUNK + 64 * 65, p = 256 * (RHS_CHUNK + 1);
+  size_t m = n > t ? n : t;
+  return (m > p ? m : p) * sizeof(double);
 }
 
 __global__ __launch_bounds__(256) void k_fwd_diag(int nb, const double* Linv, int k, const double* R, double* W,
                                                   int64_t ld, int nrhs, const int* info) {
   if (*info) return;
-  __shared__ double Vs[256 * RHS_CHUNK];
-  const int r0 = blockIdx.x * 64;
+  extern __shared__ double lds[];
+  const int r0 = blockIdx.x * GROWS;
   const int64_t off = (int64_t)k * nb;
-  tile_gemv_n(Linv + (int64_t)k * nb * nb, F64, nb, r0, R + off, ld, W + off, ld, nrhs, 0, Vs);
+  tile_gemv<false>(Linv + (int64_t)k * nb * nb, F64, nb, r0, R + off, ld, W + off, ld, nrhs, 0, lds);
 }
 
 __global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
                                                     int nrhs) {
   if (*tv.info) return;
-  __shared__ double Vs[256 * RHS_CHUNK];
-  const int nb = tv.nb, rb = nb / 64;
+  extern __shared__ double lds[];
+  const int nb = tv.nb, rb = nb / GROWS;
   const int i = k + 1 + blockIdx.x / rb;
-  const int r0 = (blockIdx.x % rb) * 64;
-  tile_gemv_n(tv.tile(i, k), tv.tfmt(i, k), nb, r0, W + (int64_t)k * nb, ld, R + (int64_t)i * nb, ld, nrhs, 1,
-              Vs);
+  const int r0 = (blockIdx.x % rb) * GROWS;
+  tile_gemv<false>(tv.tile(i, k), tv.tfmt(i, k), nb, r0, W + (int64_t)k * nb, ld, R + (int64_t)i * nb, ld, nrhs, 1,
+                   lds);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_diag(int nb, int nt, const double* Linv, int k, const double* V,
                                                   double* X, int64_t ld, int nrhs, const int* info) {
   if (*info) return;
-  __shared__ double Vs[256 * RHS_CHUNK];
-  const int r0 = blockIdx.x * 64;
+  extern __shared__ double lds[];
+  const int r0 = blockIdx.x * GROWS;
   const int64_t off = (int64_t)k * nb;
   const double* LinvT = Linv + (int64_t)nt * nb * nb + (int64_t)k * nb * nb;
-  tile_gemv_n(LinvT, F64, nb, r0, V + off, ld, X + off, ld, nrhs, 0, Vs);
+  tile_gemv<false>(LinvT, F64, nb, r0, V + off, ld, X + off, ld, nrhs, 0, lds);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
                                                     int nrhs) {
   if (*tv.info) return;
-  __shared__ double Vs[256 * RHS_CHUNK];
-  __shared__ double part[256 * RHS_CHUNK];
-  const int nb = tv.nb, rb = nb / 64;
+  extern __shared__ double lds[];
+  const int nb = tv.nb, rb = nb / GROWS;
   const int i = blockIdx.x / rb;  // i < k
-  const int r0 = (blockIdx.x % rb) * 64;
-  tile_gemv_t(tv.tile(k, i), tv.tfmt(k, i), nb, r0, X + (int64_t)k * nb, ld, V + (int64_t)i * nb, ld, nrhs, 1, Vs,
-              part);
+  const int r0 = (blockIdx.x % rb) * GROWS;
+  tile_gemv<true>(tv.tile(k, i), tv.tfmt(k, i), nb, r0, X + (int64_t)k * nb, ld, V + (int64_t)i * nb, ld, nrhs, 1,
+                  lds);
+}
+
+
+static hipError_t allow_big_lds() {
+  static hipError_t once = [] {
+    const int bytes = 160 * 1024;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_fwd_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_bwd_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+  }();
+  return once;
 }
 
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
                            int nrhs, hipStream_t s) {
-  k_fwd_diag<<<tv.nb / 64, 256, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
+  if (hipError_t e = allow_big_lds(); e != hipSuccess) return e;
+  k_fwd_diag<<<tv.nb / GROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
                              hipStream_t s) {
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
-  k_fwd_update<<<nt * (tv.nb / 64), 256, 0, s>>>(tv, k, R, W, ld, nrhs);
+  k_fwd_update<<<nt * (tv.nb / GROWS), 256, gemv_lds(tv.nb), s>>>(tv, k, R, W, ld, nrhs);
   return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
                            int nrhs, hipStream_t s) {
-  k_bwd_diag<<<tv.nb / 64, 256, 0, s>>>(tv.nb, tv.nt, Linv, k, V, X, ld, nrhs, tv.info);
+  k_bwd_diag<<<tv.nb / GROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, tv.nt, Linv, k, V, X, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* X, int64_t ld, int nrhs,
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  k_bwd_update<<<k * (tv.nb / 64), 256, 0, s>>>(tv, k, V, X, ld, nrhs);
+  k_bwd_update<<<k * (tv.nb / GROWS), 256, gemv_lds(tv.nb), s>>>(tv, k, V, X, ld, nrhs);
   return hipGetLastError();
 }
 

@@ -49,6 +49,13 @@ class mpcr_diag_t(C.Structure):
                 ("t_refine_ms", C.c_double), ("flops_by_prec", C.c_double * 5)]
 
 
+# The library must share the process's HIP runtime with PyTorch, which ships its
+# own copy of libamdhip64: load torch first so that libmpcr binds to that one.
+try:
+    import torch  # noqa: F401
+except ImportError:  # no torch: the system HIP runtime is used
+    torch = None
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build() or "
                       "python -m paper_2406_02701_amd.build)")
@@ -103,7 +110,7 @@ class MpcrError(RuntimeError):
 def check(status: int, ctx=None) -> int:
     """Raise MpcrError for a non-zero status (with the context's last error)."""
     if status != MPCR_OK:
-        msg = mpcr_last_error(ctx).decode() if ctx else ""
+        msg = mpcr_last_error(ctx).decode()
         raise MpcrError(status, msg)
     return status
 
