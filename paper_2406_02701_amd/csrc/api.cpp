@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,10 +18,70 @@
 
 using namespace mpcr;
 
+namespace mpcr {
+// First-fit sub-allocator over one device allocation, 256-byte granules.  Used
+// by the serving engine so that admitting and retiring requests never calls
+// hipMalloc / hipFree (which would serialise the device).
+hipError_t Arena::init(size_t bytes) {
+  bytes = (bytes + 255) / 256 * 256;
+  hipError_t e = hipMalloc((void**)&base_, bytes);
+  if (e != hipSuccess) return e;
+  capacity_ = bytes;
+  free_[0] = bytes;
+  return hipSuccess;
+}
+Arena::~Arena() {
+  if (base_) (void)hipFree(base_);
+}
+void* Arena::alloc(size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    size_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > bytes) free_[off + bytes] = len - bytes;
+    used_[off] = bytes;
+    in_use_ += bytes;
+    return base_ + off;
+  }
+  return nullptr;
+}
+void Arena::free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(mu_);
+  size_t off = (size_t)((char*)p - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t len = u->second;
+  used_.erase(u);
+  in_use_ -= len;
+  auto next = free_.lower_bound(off);
+  if (next != free_.end() && off + len == next->first) {  // merge with the following block
+    len += next->second;
+    free_.erase(next);
+  }
+  auto it = free_.lower_bound(off);
+  if (it != free_.begin()) {  // merge with the preceding block
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == off) {
+      prev->second += len;
+      return;
+    }
+  }
+  free_[off] = len;
+}
+size_t Arena::in_use() {
+  std::lock_guard<std::mutex> g(mu_);
+  return in_use_;
+}
+}  // namespace mpcr
+
 constexpr int NKIND = 10;  // kernel kinds timed by the context (see mpcr_ctx_kernel_stats)
 
 struct mpcr_ctx {
   int device = 0;
+  Arena* arena = nullptr;  // device allocations come from here when set (serving workers)
   hipStream_t stream = nullptr;
   std::string err;
   // workspace reused across mpcr_gauss_loglik calls of the same shape
@@ -114,6 +176,7 @@ struct mpcr_factor {
   std::vector<int> task_cnt_next;  // leading tasks of each list that update column k+1
   double flops[5] = {0, 0, 0, 0, 0};
   int64_t info = 0;
+  Arena* arena = nullptr;  // allocator the device buffers came from (NULL: hipMalloc)
 
   TileView view() const {
     TileView tv;
@@ -167,22 +230,28 @@ struct DeviceGuard {
   }
 };
 
+// Device allocation from the arena when one is given, else hipMalloc.
 template <class T>
-hipError_t dmalloc(T** p, size_t bytes) {
+hipError_t dmalloc(Arena* a, T** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (a) {
+    *p = (T*)a->alloc(bytes);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
   return hipMalloc((void**)p, bytes);
+}
+void dfree(Arena* a, void* p) {
+  if (!p) return;
+  if (a) a->free(p);
+  else (void)hipFree(p);
 }
 
 void free_factor(mpcr_factor* f) {
   if (!f) return;
   DeviceGuard g(f->device);
-  (void)hipFree(f->d_base);
-  (void)hipFree(f->d_off);
-  (void)hipFree(f->d_fmt);
-  (void)hipFree(f->d_info);
-  (void)hipFree(f->d_trsm_ws);
-  (void)hipFree(f->d_Linv);
-  (void)hipFree(f->d_tasks);
+  for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
+                  (void*)f->d_Linv, (void*)f->d_tasks})
+    dfree(f->arena, p);
   delete f;
 }
 
@@ -214,6 +283,7 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
   DeviceGuard g(ctx->device);
   auto* f = new mpcr_factor();
   f->device = ctx->device;
+  f->arena = ctx->arena;
   f->n = n;
   f->nb = nb;
   f->nt = (n + nb - 1) / nb;
@@ -255,10 +325,11 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
     }
   }
   hipError_t e;
-  if ((e = dmalloc(&f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(&f->d_off, ntiles * 8)) != hipSuccess ||
-      (e = dmalloc(&f->d_fmt, ntiles)) != hipSuccess || (e = dmalloc(&f->d_info, sizeof(int))) != hipSuccess ||
-      (e = dmalloc(&f->d_trsm_ws, (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 8)) != hipSuccess ||
-      (e = dmalloc(&f->d_tasks, std::max<size_t>(tasks.size(), 1) * sizeof(GemmTask))) != hipSuccess) {
+  Arena* A = f->arena;
+  if ((e = dmalloc(A, &f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(A, &f->d_off, ntiles * 8)) != hipSuccess ||
+      (e = dmalloc(A, &f->d_fmt, ntiles)) != hipSuccess || (e = dmalloc(A, &f->d_info, sizeof(int))) != hipSuccess ||
+      (e = dmalloc(A, &f->d_trsm_ws, (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 8)) != hipSuccess ||
+      (e = dmalloc(A, &f->d_tasks, std::max<size_t>(tasks.size(), 1) * sizeof(GemmTask))) != hipSuccess) {
     free_factor(f);
     return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
@@ -338,7 +409,7 @@ int read_info(mpcr_ctx* ctx, mpcr_factor* f, int64_t* h_info) {
 
 int ensure_linv(mpcr_ctx* ctx, mpcr_factor* f) {
   if (f->linv_ready) return MPCR_OK;
-  if (!f->d_Linv) HIP_TRY(ctx, dmalloc(&f->d_Linv, (size_t)2 * f->nt * f->nb * f->nb * 8));
+  if (!f->d_Linv) HIP_TRY(ctx, dmalloc(f->arena, &f->d_Linv, (size_t)2 * f->nt * f->nb * f->nb * 8));
   const double nb3 = (double)f->nb * f->nb * f->nb;
   HIP_TRY(ctx, timed(ctx, ctx->stream, 7, nb3 / 3.0 * (double)f->nt,
                      [&] { return launch_trtri_diag(f->view(), f->d_Linv, ctx->stream); }));
@@ -365,10 +436,10 @@ int64_t solve_bytes(int64_t N, int64_t nrhs, int64_t n) {
 int carve(mpcr_ctx* ctx, int64_t N, int64_t nrhs, int64_t n, SolveBufs& b) {
   int64_t need = solve_bytes(N, nrhs, n);
   if (ctx->ws_vec_bytes < need) {
-    if (ctx->ws_vec) (void)hipFree(ctx->ws_vec);
+    dfree(ctx->arena, ctx->ws_vec);
     ctx->ws_vec = nullptr;
     ctx->ws_vec_bytes = 0;
-    HIP_TRY(ctx, dmalloc(&ctx->ws_vec, (size_t)need));
+    HIP_TRY(ctx, dmalloc(ctx->arena, &ctx->ws_vec, (size_t)need));
     ctx->ws_vec_bytes = need;
   }
   char* p = (char*)ctx->ws_vec;
@@ -426,10 +497,11 @@ struct SigmaOp {
   const double* A = nullptr;
   int64_t lda = 0;
   int n = 0;
-  hipError_t residual(const double* B, const double* X, double* R, int64_t ld, int nrhs, hipStream_t s) const {
+  hipError_t residual(const double* B, const double* X, double* R, int64_t ld, int nrhs, hipStream_t s,
+                      double* rowsum = nullptr) const {
     auto go = [&] {
-      return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s)
-               : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s);
+      return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s, rowsum)
+               : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s, rowsum);
     };
     return ctx ? timed(ctx, s, 9, 2.0 * (double)n * n * nrhs, go) : go();
   }
@@ -452,8 +524,6 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
   double* rzn = b.scal + 5 * nrhs;
   double* stats = b.scal + 6 * nrhs;       // 2 nrhs
   double* rowsum = b.Z;                    // temporary use before Z is needed
-  HIP_TRY(ctx, op.rowsum(rowsum, s));
-  HIP_TRY(ctx, launch_max_reduce(n, rowsum, b.partial, sig_inf, s));
 
   std::vector<double> hst(2 * nrhs);
   std::vector<int> act(nrhs, 1);
@@ -470,9 +540,10 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
   };
 
   int rc;
-  // x0 = M^{-1} b, r0 = b - Sigma x0
+  // x0 = M^{-1} b, r0 = b - Sigma x0 (the same pass gives ||Sigma||_inf)
   if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;
-  HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+  HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s, rowsum));
+  HIP_TRY(ctx, launch_max_reduce(n, rowsum, b.partial, sig_inf, s));
   if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
   int nact = 0;
   for (int c = 0; c < nrhs; ++c) {
@@ -597,8 +668,8 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     free_factor(ctx->ws_factor);
-    (void)hipFree(ctx->ws_locs);
-    (void)hipFree(ctx->ws_vec);
+    dfree(ctx->arena, ctx->ws_locs);
+    dfree(ctx->arena, ctx->ws_vec);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     drain_timing(ctx);
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -698,13 +769,13 @@ int mpcr_morton_order(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d
   int npow2 = 1;
   while (npow2 < n) npow2 <<= 1;
   uint64_t* keys = nullptr;
-  HIP_TRY(ctx, dmalloc(&keys, (size_t)npow2 * 8));
+  HIP_TRY(ctx, dmalloc(ctx->arena, &keys, (size_t)npow2 * 8));
   hipStream_t s = ctx->stream;
   hipError_t e = launch_morton_codes((int)n, d_locs, keys, npow2, s);
   if (e == hipSuccess) e = launch_bitonic_sort(keys, npow2, s);
   if (e == hipSuccess) e = launch_keys_to_perm((int)n, keys, d_perm_out, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(keys);
+  dfree(ctx->arena, keys);
   HIP_TRY(ctx, e);
   return MPCR_OK;
 }
@@ -739,12 +810,12 @@ int mpcr_covariance_tile_amax(mpcr_ctx* ctx, int64_t n, int64_t nb, const double
   DeviceGuard g(ctx->device);
   int64_t nt = (n + nb - 1) / nb;
   double* d = nullptr;
-  HIP_TRY(ctx, dmalloc(&d, (size_t)nt * nt * 8));
+  HIP_TRY(ctx, dmalloc(ctx->arena, &d, (size_t)nt * nt * 8));
   hipError_t e = hipMemsetAsync(d, 0, nt * nt * 8, ctx->stream);
   if (e == hipSuccess) e = launch_covariance_tile_amax((int)n, (int)nb, d_locs, *theta, d, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h_amax_out, d, nt * nt * 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  (void)hipFree(d);
+  dfree(ctx->arena, d);
   HIP_TRY(ctx, e);
   return MPCR_OK;
 }
@@ -802,11 +873,11 @@ int mpcr_factor_logdet(mpcr_ctx* ctx, const mpcr_factor* fc, double* h_logdet) {
   CHECK_ARG(ctx, fc->info == 0, "factor is not positive definite (info %lld)", (long long)fc->info);
   DeviceGuard g(ctx->device);
   double* d = nullptr;
-  HIP_TRY(ctx, dmalloc(&d, 8));
+  HIP_TRY(ctx, dmalloc(ctx->arena, &d, 8));
   hipError_t e = launch_logdet(fc->view(), d, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h_logdet, d, 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  (void)hipFree(d);
+  dfree(ctx->arena, d);
   HIP_TRY(ctx, e);
   return MPCR_OK;
 }
@@ -921,11 +992,11 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   if (!ctx->ws_factor || ctx->ws_n != n || ctx->ws_nb != nb || ctx->ws_map != m) {
     free_factor(ctx->ws_factor);
     ctx->ws_factor = nullptr;
-    (void)hipFree(ctx->ws_locs);
+    dfree(ctx->arena, ctx->ws_locs);
     ctx->ws_locs = nullptr;
     ctx->ws_n = -1;
     if ((rc = make_factor(ctx, n, nb, m, &ctx->ws_factor)) != MPCR_OK) return rc;
-    HIP_TRY(ctx, dmalloc(&ctx->ws_locs, (size_t)n * 2 * 8 + (size_t)n * 8));
+    HIP_TRY(ctx, dmalloc(ctx->arena, &ctx->ws_locs, (size_t)n * 2 * 8 + (size_t)n * 8));
     ctx->ws_n = n;
     ctx->ws_nb = nb;
     ctx->ws_map = m;
@@ -946,7 +1017,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     if ((int64_t)npow2 * 8 <= 3 * f->N * nrhs * 8) {
       keys = (uint64_t*)b.P;
     } else {
-      HIP_TRY(ctx, dmalloc(&keys, (size_t)npow2 * 8));
+      HIP_TRY(ctx, dmalloc(ctx->arena, &keys, (size_t)npow2 * 8));
       own = true;
     }
     hipError_t e = launch_morton_codes((int)n, d_locs, keys, npow2, s);
@@ -956,7 +1027,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     if (e == hipSuccess) e = launch_gather_rows((int)n, (int)nrhs, d_Z, n, perm, b.B, b.N, s);
     if (own) {
       (void)hipStreamSynchronize(s);
-      (void)hipFree(keys);
+      dfree(ctx->arena, keys);
     }
     HIP_TRY(ctx, e);
     HIP_TRY(ctx, launch_fill(b.P, 3 * b.N * nrhs, 0.0, s));
@@ -999,9 +1070,8 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
       op.n = (int)n;
       double* sig_inf = b.scal;
       double* stats = b.scal + 6 * nrhs;
-      HIP_TRY(ctx, op.rowsum(b.Z, s));
+      HIP_TRY(ctx, op.residual(b.B, b.X, b.R, b.N, (int)nrhs, s, b.Z));
       HIP_TRY(ctx, launch_max_reduce((int)n, b.Z, b.partial, sig_inf, s));
-      HIP_TRY(ctx, op.residual(b.B, b.X, b.R, b.N, (int)nrhs, s));
       HIP_TRY(ctx, launch_col_stats((int)n, (int)nrhs, b.R, b.X, b.B, b.N, sig_inf, b.partial, stats, s));
       std::vector<double> hst(2 * nrhs);
       HIP_TRY(ctx, hipMemcpyAsync(hst.data(), stats, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));

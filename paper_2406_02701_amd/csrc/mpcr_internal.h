@@ -137,6 +137,32 @@ struct GemmTask {
 
 }  // namespace mpcr
 
+#include <map>
+#include <mutex>
+#include <unordered_map>
+namespace mpcr {
+// Device memory arena (host-side bookkeeping; see api.cpp).
+class Arena {
+ public:
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena();
+  hipError_t init(size_t bytes);
+  void* alloc(size_t bytes);  // NULL when no free block is large enough
+  void free(void* p);
+  size_t capacity() const { return capacity_; }
+  size_t in_use();
+
+ private:
+  std::mutex mu_;
+  char* base_ = nullptr;
+  size_t capacity_ = 0, in_use_ = 0;
+  std::map<size_t, size_t> free_;            // offset -> length
+  std::unordered_map<size_t, size_t> used_;  // offset -> length
+};
+}  // namespace mpcr
+
 // ---------------------------------------------------------------------------
 // kernel launchers (defined in the .hip files, called by the host driver)
 // ---------------------------------------------------------------------------
@@ -169,10 +195,12 @@ hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double
 hipError_t launch_bwd_update(const TileView& tv, int k, double* R, const double* X, int64_t ld, int nrhs,
                              hipStream_t s);
 
+// R = B - Sigma X (B == NULL: R = -Sigma X); rowsum != NULL also receives sum_c |Sigma_rc|
 hipError_t launch_residual_cov(int n, const double* locs, const mpcr_theta_t& th, const double* B,
-                               const double* X, double* R, int64_t ld, int nrhs, hipStream_t s);
+                               const double* X, double* R, int64_t ld, int nrhs, hipStream_t s,
+                               double* rowsum = nullptr);
 hipError_t launch_residual_dense(int n, const double* A, int64_t lda, const double* B, const double* X,
-                                 double* R, int64_t ld, int nrhs, hipStream_t s);
+                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum = nullptr);
 hipError_t launch_rowsum_abs_cov(int n, const double* locs, const mpcr_theta_t& th, double* out,
                                  hipStream_t s);
 hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* out, hipStream_t s);

@@ -13,8 +13,9 @@
 namespace mpcr {
 
 constexpr int RHS_CHUNK = 16;
-constexpr int GROWS = 64;    // output rows per workgroup
-constexpr int GSPLIT = 4;    // k-split of the 256 threads (64 rows x 4)
+constexpr int GROWS = 64;    // output rows per workgroup of the panel products (64 rows x 4-way k split)
+constexpr int DROWS = 16;    // output rows per workgroup of the diagonal products (16 rows x 16-way k split):
+                             // only nb / DROWS workgroups run per step, so each does little
 
 template <int F>
 __device__ __forceinline__ double ldw(const void* p, int64_t i) {
@@ -30,12 +31,13 @@ __device__ __forceinline__ double ldw(const void* p, int64_t i) {
 // sixteen right-hand sides in registers; V is staged in LDS (k-major, 16
 // values per k, read as broadcasts); the four quarters are added in a fixed
 // order.  mode 0: out = M V, mode 1: out -= M V.
-template <int F>
+template <int F, int ROWS>
 __device__ void gemv_n_rows(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
                             int nrhs, int mode, double* Vs /* nb x 16 */) {
-  const int tid = threadIdx.x, r = tid & 63, h = tid >> 6;
+  constexpr int KS = 256 / ROWS;  // k-split of the 256 threads
+  const int tid = threadIdx.x, r = tid % ROWS, h = tid / ROWS;
+  const int kq = nb / KS, kb = h * kq;
   double* part = Vs;  // 256 x 17 partial sums, written once the products are done
-  const int kq = nb / GSPLIT, kb = h * kq;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     __syncthreads();
@@ -48,7 +50,7 @@ __device__ void gemv_n_rows(const void* M, int nb, int r0, const double* V, int6
 #pragma unroll
     for (int j = 0; j < RHS_CHUNK; ++j) acc[j] = 0.0;
     const int64_t base = (int64_t)r0 + r;
-#pragma unroll 4
+#pragma unroll 8
     for (int k = kb; k < kb + kq; ++k) {
       const double m = ldw<F>(M, (int64_t)k * nb + base);
       const double* vk = Vs + k * RHS_CHUNK;
@@ -59,12 +61,11 @@ __device__ void gemv_n_rows(const void* M, int nb, int r0, const double* V, int6
 #pragma unroll
     for (int j = 0; j < RHS_CHUNK; ++j) part[tid * (RHS_CHUNK + 1) + j] = acc[j];
     __syncthreads();
-    for (int e = tid; e < GROWS * RHS_CHUNK; e += 256) {
-      const int rr = e % GROWS, j = e / GROWS;
+    for (int e = tid; e < ROWS * RHS_CHUNK; e += 256) {
+      const int rr = e % ROWS, j = e / ROWS;
       if (j < nc) {
         double sum = 0.0;
-#pragma unroll
-        for (int q = 0; q < GSPLIT; ++q) sum += part[(q * 64 + rr) * (RHS_CHUNK + 1) + j];
+        for (int q = 0; q < KS; ++q) sum += part[(q * ROWS + rr) * (RHS_CHUNK + 1) + j];
         double* o = out + (int64_t)(c0 + j) * ldo + r0 + rr;
         *o = mode == 0 ? sum : *o - sum;
       }
@@ -115,13 +116,13 @@ __device__ void gemv_t_rows(const void* M, int nb, int r0, const double* V, int6
   }
 }
 
-template <bool TRANS>
+template <bool TRANS, int ROWS>
 __device__ void tile_gemv(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
                           int64_t ldo, int nrhs, int mode, double* lds) {
 #define MPCR_GEMV_CASE(FMT)                                                                   \
   case FMT:                                                                                  \
     if (TRANS) gemv_t_rows<FMT>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);               \
-    else gemv_n_rows<FMT>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);                     \
+    else gemv_n_rows<FMT, ROWS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);               \
     break;
   switch (f) {
     MPCR_GEMV_CASE(F64)
@@ -146,9 +147,9 @@ __global__ __launch_bounds__(256) void k_fwd_diag(int nb, const double* Linv, in
                                                   int64_t ld, int nrhs, const int* info) {
   if (*info) return;
   extern __shared__ double lds[];
-  const int r0 = blockIdx.x * GROWS;
+  const int r0 = blockIdx.x * DROWS;
   const int64_t off = (int64_t)k * nb;
-  tile_gemv<false>(Linv + (int64_t)k * nb * nb, F64, nb, r0, R + off, ld, W + off, ld, nrhs, 0, lds);
+  tile_gemv<false, DROWS>(Linv + (int64_t)k * nb * nb, F64, nb, r0, R + off, ld, W + off, ld, nrhs, 0, lds);
 }
 
 __global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* 
   const int nb = tv.nb, rb = nb / GROWS;
   const int i = k + 1 + blockIdx.x / rb;
   const int r0 = (blockIdx.x % rb) * GROWS;
-  tile_gemv<false>(tv.tile(i, k), tv.tfmt(i, k), nb, r0, W + (int64_t)k * nb, ld, R + (int64_t)i * nb, ld, nrhs, 1,
+  tile_gemv<false, GROWS>(tv.tile(i, k), tv.tfmt(i, k), nb, r0, W + (int64_t)k * nb, ld, R + (int64_t)i * nb, ld, nrhs, 1,
                    lds);
 }
 
@@ -166,10 +167,10 @@ __global__ __launch_bounds__(256) void k_bwd_diag(int nb, int nt, const double* 
                                                   double* X, int64_t ld, int nrhs, const int* info) {
   if (*info) return;
   extern __shared__ double lds[];
-  const int r0 = blockIdx.x * GROWS;
+  const int r0 = blockIdx.x * DROWS;
   const int64_t off = (int64_t)k * nb;
   const double* LinvT = Linv + (int64_t)nt * nb * nb + (int64_t)k * nb * nb;
-  tile_gemv<false>(LinvT, F64, nb, r0, V + off, ld, X + off, ld, nrhs, 0, lds);
+  tile_gemv<false, DROWS>(LinvT, F64, nb, r0, V + off, ld, X + off, ld, nrhs, 0, lds);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* 
   const int nb = tv.nb, rb = nb / GROWS;
   const int i = blockIdx.x / rb;  // i < k
   const int r0 = (blockIdx.x % rb) * GROWS;
-  tile_gemv<true>(tv.tile(k, i), tv.tfmt(k, i), nb, r0, X + (int64_t)k * nb, ld, V + (int64_t)i * nb, ld, nrhs, 1,
+  tile_gemv<true, GROWS>(tv.tile(k, i), tv.tfmt(k, i), nb, r0, X + (int64_t)k * nb, ld, V + (int64_t)i * nb, ld, nrhs, 1,
                   lds);
 }
 
@@ -202,7 +203,7 @@ static hipError_t allow_big_lds() {
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
                            int nrhs, hipStream_t s) {
   if (hipError_t e = allow_big_lds(); e != hipSuccess) return e;
-  k_fwd_diag<<<tv.nb / GROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
+  k_fwd_diag<<<tv.nb / DROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
@@ -214,7 +215,7 @@ hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double*
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
                            int nrhs, hipStream_t s) {
-  k_bwd_diag<<<tv.nb / GROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, tv.nt, Linv, k, V, X, ld, nrhs, tv.info);
+  k_bwd_diag<<<tv.nb / DROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, tv.nt, Linv, k, V, X, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* X, int64_t ld, int nrhs,
@@ -244,11 +245,12 @@ static int nu_code_s(double nu) { return nu == 0.5 ? 0 : (nu == 1.5 ? 1 : 2); }
 template <int MODE, bool DENSE>
 __global__ __launch_bounds__(256) void k_sigma_apply(int n, const double* locs, double s2, double range, int nuc,
                                                      double nugget, const double* A, int64_t lda, const double* B,
-                                                     const double* X, double* R, int64_t ld, int nrhs) {
+                                                     const double* X, double* R, int64_t ld, int nrhs,
+                                                     double* rowsum) {
   constexpr int CC = 256;
   __shared__ double Ls[2][CC];
   __shared__ double Xs[CC * RHS_CHUNK];
-  __shared__ double part[4][64][RHS_CHUNK + 1];
+  __shared__ double part[4][64][RHS_CHUNK + 1];  // [.][.][RHS_CHUNK]: |Sigma| row sums
   const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
   const int row = blockIdx.x * 64 + r;
   const bool live = row < n;
@@ -257,6 +259,7 @@ __global__ __launch_bounds__(256) void k_sigma_apply(int n, const double* locs, 
   const int ncol = MODE == 1 ? 1 : nrhs;
   for (int c0 = 0; c0 < ncol; c0 += RHS_CHUNK) {
     double acc[RHS_CHUNK];
+    double asum = 0.0;  // sum_c |Sigma_rc| when rowsum is requested (first chunk only)
 #pragma unroll
     for (int j = 0; j < RHS_CHUNK; ++j) acc[j] = 0.0;
     for (int k0 = 0; k0 < n; k0 += CC) {
@@ -289,6 +292,7 @@ __global__ __launch_bounds__(256) void k_sigma_apply(int n, const double* locs, 
           if (MODE == 1) {
             acc[0] += fabs(sv);
           } else {
+            asum += fabs(sv);
 #pragma unroll
             for (int j = 0; j < RHS_CHUNK; ++j) acc[j] += sv * Xs[kk * RHS_CHUNK + j];
           }
@@ -298,7 +302,11 @@ __global__ __launch_bounds__(256) void k_sigma_apply(int n, const double* locs, 
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < RHS_CHUNK; ++j) part[q][r][j] = acc[j];
+    part[q][r][RHS_CHUNK] = asum;
     __syncthreads();
+    if (MODE == 0 && rowsum && c0 == 0 && tid < 64 && blockIdx.x * 64 + tid < n)
+      rowsum[blockIdx.x * 64 + tid] = ((part[0][tid][RHS_CHUNK] + part[1][tid][RHS_CHUNK]) + part[2][tid][RHS_CHUNK]) +
+                                      part[3][tid][RHS_CHUNK];
     for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
       int rr = e % 64, j = e / 64;
       int grow = blockIdx.x * 64 + rr, c = c0 + j;
@@ -314,27 +322,28 @@ __global__ __launch_bounds__(256) void k_sigma_apply(int n, const double* locs, 
 }
 
 hipError_t launch_residual_cov(int n, const double* locs, const mpcr_theta_t& th, const double* B, const double* X,
-                               double* R, int64_t ld, int nrhs, hipStream_t s) {
+                               double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum) {
   if (n == 0) return hipSuccess;
   k_sigma_apply<0, false><<<(n + 63) / 64, 256, 0, s>>>(n, locs, th.sigma2, th.range, nu_code_s(th.nu), th.nugget,
-                                                        nullptr, 0, B, X, R, ld, nrhs);
+                                                        nullptr, 0, B, X, R, ld, nrhs, rowsum);
   return hipGetLastError();
 }
 hipError_t launch_residual_dense(int n, const double* A, int64_t lda, const double* B, const double* X, double* R,
-                                 int64_t ld, int nrhs, hipStream_t s) {
+                                 int64_t ld, int nrhs, hipStream_t s, double* rowsum) {
   if (n == 0) return hipSuccess;
-  k_sigma_apply<0, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, B, X, R, ld, nrhs);
+  k_sigma_apply<0, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, B, X, R, ld, nrhs, rowsum);
   return hipGetLastError();
 }
 hipError_t launch_rowsum_abs_cov(int n, const double* locs, const mpcr_theta_t& th, double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_sigma_apply<1, false><<<(n + 63) / 64, 256, 0, s>>>(n, locs, th.sigma2, th.range, nu_code_s(th.nu), th.nugget,
-                                                        nullptr, 0, nullptr, nullptr, out, 0, 1);
+                                                        nullptr, 0, nullptr, nullptr, out, 0, 1, nullptr);
   return hipGetLastError();
 }
 hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_sigma_apply<1, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, nullptr, nullptr, out, 0, 1);
+  k_sigma_apply<1, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, nullptr, nullptr, out, 0, 1,
+                                                       nullptr);
   return hipGetLastError();
 }
 
