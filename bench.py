@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-gemm", action="store_true", help="skip the multi-format GEMM sweep")
+    ap.add_argument("--serve-count", type=int, default=4096, help="serving requests (0 = skip the serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--guard", type=float, default=0.01,
                     help="norm guard of the tile map, as a multiple of the nugget: a tile keeps its band format p "
                          "only if u_p max|Sigma_tile| <= guard * nugget")
@@ -191,6 +194,66 @@ def gemm_sweep(lib, torch, steps):
     return out
 
 
+def serving_bench(lib, count, slots, budget_gb, seed=6):
+    """Log-likelihood requests with n log-uniform in [256, 8192] and their own
+    parameters (variance U(0.5,2), range U(0.02,0.3), nu in {1/2, 3/2, 5/2},
+    nugget 1e-6), one observation vector each.  Phase 1 submits all requests at
+    once (closed-loop capacity, solves/s); phase 2 replays Poisson arrivals at
+    0.8 x that capacity and reports the latency (done - arrival) percentiles."""
+    mp = lib.m
+    w = synth.WORKLOADS["serve_4096"]
+    reqs = synth.serving_requests(count, seed, w["n_lo"], w["n_hi"])
+    arrays = []
+    for r in reqs:
+        locs, z = synth.request_arrays(r)
+        arrays.append((np.asfortranarray(locs), np.ascontiguousarray(z[:, 0]),
+                       mp.mpcr_theta_t(r["sigma2"], r["range"], r["nu"], r["nugget"])))
+    opts = mp.mpcr_serve_opts_t(w["nb"], 1, 4, mp.MPCR_BF16, 0.01, mp.mpcr_refine_opts_t(1e-13, 100, 0, 20, 0), 1)
+
+    def run(arrival):
+        srv = ctypes.c_void_p()
+        mp.check(mp.mpcr_serve_create(0, int(budget_gb * (1 << 30)), slots, ctypes.byref(opts), ctypes.byref(srv)))
+        t_base = mp.mpcr_serve_clock(srv)
+        res, nsub, rejected = {}, 0, 0
+        rid, ll, st, fb = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+        ts, td = ctypes.c_double(), ctypes.c_double()
+
+        def poll_all():
+            while mp.mpcr_serve_poll(srv, ctypes.byref(rid), ctypes.byref(ll), None, ctypes.byref(ts),
+                                     ctypes.byref(td), ctypes.byref(st), ctypes.byref(fb)) == 1:
+                res[rid.value] = (ts.value, td.value, st.value, fb.value, ll.value)
+        while nsub < count:
+            now = mp.mpcr_serve_clock(srv) - t_base
+            while nsub < count and arrival[nsub] <= now:
+                locs, z, th = arrays[nsub]
+                rc = mp.mpcr_serve_submit(srv, nsub, reqs[nsub]["n"], mp.f64p(locs), mp.f64p(z), ctypes.byref(th))
+                rejected += rc == mp.MPCR_ERR_REJECTED
+                nsub += 1
+            poll_all()
+            time.sleep(0.0002)
+        while len(res) + rejected < count:
+            poll_all()
+            time.sleep(0.0005)
+        t_end = max(v[1] for v in res.values()) - t_base
+        mp.mpcr_serve_destroy(srv)
+        lat = np.array([v[1] - (t_base + arrival[k]) for k, v in res.items()])
+        ok = sum(1 for v in res.values() if v[2] == 0)
+        return dict(wall_s=t_end, solves_per_s=ok / t_end, completed_ok=ok, rejected=rejected,
+                    failed=len(res) - ok, fallback_fp64=sum(v[3] for v in res.values()),
+                    p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    mean_ms=float(lat.mean() * 1e3))
+
+    closed = run(np.zeros(count))
+    qps = 0.8 * closed["solves_per_s"]
+    gaps = synth.rng(seed + 100).exponential(1.0 / qps, size=count)
+    poisson = run(np.cumsum(gaps) - gaps[0])
+    flops = sum(r["n"] ** 3 / 3 + 2 * r["n"] ** 2 for r in reqs)
+    return {"requests": count, "slots": slots, "hbm_budget_gb": budget_gb, "nb": w["nb"],
+            "map": "band d<=1 fp64 / 2-4 fp32 / rest bf16, norm-guarded 0.01 nugget, fp64 fallback",
+            "closed_loop": closed, "poisson_qps": qps, "poisson": poisson,
+            "closed_loop_tflops": flops / closed["wall_s"] / 1e12}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -305,6 +368,8 @@ def main():
     mp.mpcr_ctx_destroy(ctx_d)
     if not args.no_gemm:
         line["gemm_sweep_8192"] = gemm_sweep(lib, torch, 3)
+    if args.serve_count > 0:
+        line["serving"] = serving_bench(lib, args.serve_count, args.serve_slots, args.serve_budget_gb)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_n, n))
     print(json.dumps(line), flush=True)

@@ -277,6 +277,55 @@ int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m
               const void* d_B, int64_t ldb, const int8_t* d_scaleB_exp, double beta, void* d_C,
               int64_t ldc, mpcr_prec_t c_prec);
 
+/* ---- serving: continuous batching of log-likelihood requests ------------------ */
+
+/* A server owns a pre-allocated device arena of hbm_budget bytes and max_slots
+ * worker slots; each slot has its own context and HIP stream, so requests on
+ * different slots run concurrently on the device.  Requests wait in a FIFO
+ * queue and are admitted when a slot is free and their estimated device
+ * footprint fits in the unreserved part of the budget; their buffers come
+ * from the arena (no hipMalloc / hipFree per request).  Each request is one
+ * mpcr_gauss_loglik evaluation (sites in Morton order, one observation
+ * vector) with the norm-guarded banded map below; a request whose mixed
+ * factor breaks down is recomputed with all tiles FP64 (fallback).  A
+ * request's arithmetic does not depend on what else is running: results are
+ * the same alone and in a mix. */
+typedef struct mpcr_server mpcr_server;
+
+typedef struct {
+  int64_t nb;              /* tile size (multiple of 128) */
+  int band_fp64;           /* tiles with distance d <= band_fp64 are FP64 */
+  int band_fp32;           /* band_fp64 < d <= band_fp32: FP32; beyond: far_prec */
+  int far_prec;            /* mpcr_prec_t of the far tiles (FP16 or BF16) */
+  double guard;            /* norm guard relative to the nugget (<= 0: no guard) */
+  mpcr_refine_opts_t refine;
+  int fallback_fp64;       /* 1: recompute with an all-FP64 map on breakdown */
+} mpcr_serve_opts_t;
+
+/* Errors: MPCR_ERR_ARG, MPCR_ERR_NOMEM (budget cannot be allocated). */
+int mpcr_serve_create(int device, size_t hbm_budget, int max_slots, const mpcr_serve_opts_t* opts,
+                      mpcr_server** out);
+/* Waits for the requests in flight, drops queued ones, frees everything. */
+int mpcr_serve_destroy(mpcr_server* srv);
+/* Queues a request (h_locs: n x 2 column-major host array, h_z: n host
+ * values; both copied before the call returns).  Returns MPCR_ERR_REJECTED if
+ * the request's footprint exceeds the whole budget. */
+int mpcr_serve_submit(mpcr_server* srv, uint64_t req_id, int64_t n, const double* h_locs, const double* h_z,
+                      const mpcr_theta_t* theta);
+/* Takes one finished request, if any: returns 1 and fills the outputs (status
+ * = that request's mpcr_status_t, used_fallback = 1 if the FP64 map was
+ * needed; times in seconds on the server's monotonic clock), 0 if none is
+ * ready.  Any output pointer may be NULL. */
+int mpcr_serve_poll(mpcr_server* srv, uint64_t* req_id, double* loglik, mpcr_diag_t* diag, double* t_submit,
+                    double* t_done, int* status, int* used_fallback);
+/* Seconds on the server's monotonic clock (the clock of t_submit / t_done). */
+double mpcr_serve_clock(const mpcr_server* srv);
+/* Counters: queued, running, finished (not yet polled), rejected; bytes reserved. */
+int mpcr_serve_stats(mpcr_server* srv, int64_t* queued, int64_t* running, int64_t* finished, int64_t* rejected,
+                     size_t* bytes_reserved);
+/* Estimated device bytes of one request of order n (nb, one observation vector). */
+size_t mpcr_serve_footprint(int64_t n, int64_t nb);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,7 @@ constexpr int NKIND = 10;  // kernel kinds timed by the context (see mpcr_ctx_ke
 struct mpcr_ctx {
   int device = 0;
   Arena* arena = nullptr;  // device allocations come from here when set (serving workers)
+  bool own_stream = false;
   hipStream_t stream = nullptr;
   std::string err;
   // workspace reused across mpcr_gauss_loglik calls of the same shape
@@ -635,6 +636,57 @@ float ev_ms(hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 // ===========================================================================
+// internal helpers for the serving engine
+// ===========================================================================
+namespace mpcr {
+int ctx_create_with_arena(int device, Arena* arena, mpcr_ctx** out) {
+  DeviceGuard g(device);
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
+  if (e != hipSuccess) return set_err(nullptr, MPCR_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+  int rc = mpcr_ctx_create(device, (void*)s, out);
+  if (rc != MPCR_OK) {
+    (void)hipStreamDestroy(s);
+    return rc;
+  }
+  (*out)->arena = arena;
+  (*out)->own_stream = true;
+  return MPCR_OK;
+}
+
+void ctx_release_workspace(mpcr_ctx* ctx) {
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_factor(ctx->ws_factor);
+  ctx->ws_factor = nullptr;
+  ctx->ws_map.clear();
+  ctx->ws_n = ctx->ws_nb = -1;
+  dfree(ctx->arena, ctx->ws_locs);
+  ctx->ws_locs = nullptr;
+  dfree(ctx->arena, ctx->ws_vec);
+  ctx->ws_vec = nullptr;
+  ctx->ws_vec_bytes = 0;
+}
+
+hipStream_t ctx_stream(mpcr_ctx* ctx) { return ctx->stream; }
+
+size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
+  const int64_t nt = (n + nb - 1) / nb, N = nt * nb;
+  const int64_t tile = nb * nb * 8;
+  size_t bytes = 0;
+  bytes += (size_t)(nt * (nt + 1) / 2) * tile;            // tiles (FP64 bound)
+  bytes += (size_t)std::max<int64_t>(nt - 1, 1) * tile;     // TRSM workspace
+  bytes += (size_t)2 * nt * tile;                           // inverted diagonal tiles
+  bytes += (size_t)solve_bytes(N, nrhs, n);                 // vectors
+  bytes += (size_t)n * 24 + (size_t)nt * nt * 16 + 65536;   // sites, permutation, tables
+  size_t npow2 = 1;
+  while ((int64_t)npow2 < n) npow2 <<= 1;
+  bytes += npow2 * 8;                                       // ordering keys
+  return bytes + (bytes >> 5);                              // allocator granules
+}
+}  // namespace mpcr
+
+// ===========================================================================
 // exported entry points
 // ===========================================================================
 extern "C" {
@@ -675,6 +727,7 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto& e : ctx->sync_ev) (void)hipEventDestroy(e);
     if (ctx->upd) (void)hipStreamDestroy(ctx->upd);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
   return MPCR_OK;

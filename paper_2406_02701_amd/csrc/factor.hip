@@ -111,8 +111,9 @@ __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const
 
   const int nb = tv.nb;
   const int sub = nb / UBM;
-  const int task = blockIdx.x / (sub * sub);
-  const int blk = blockIdx.x % (sub * sub);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int task = lb / (sub * sub);
+  const int blk = lb % (sub * sub);
   const int bm = blk % sub, bn = blk / sub;
   const GemmTask t = tasks[task];
   if (t.i == t.j && bn > bm) return;
@@ -231,8 +232,9 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
 
   const int nb = tv.nb;
   const int sub = nb / UBM;
-  const int task = blockIdx.x / (sub * sub);
-  const int blk = blockIdx.x % (sub * sub);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int task = lb / (sub * sub);
+  const int blk = lb % (sub * sub);
   const int bm = blk % sub, bn = blk / sub;
   const GemmTask t = tasks[task];
   if (t.i == t.j && bn > bm) return;
@@ -339,15 +341,14 @@ hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTas
 constexpr int PW = 32;
 constexpr int POTRF_THREADS = 512;
 
-// acc0/acc1 (16 x 16 each) += A[R0.., 0:K] * B[C0.., 0:K]^T, operands read
-// straight from column-major FP64 storage (lda = ldb = ld), 16 k values per
-// batch so that twelve loads are in flight before the eight MFMAs use them.
-__device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B, int64_t ld, int R0, int C0, int K,
-                                               int lane, d4& acc0, d4& acc1) {
+// acc0/acc1 (16 x 16 each) += A[R0.., K0:K1] * B[C0.., K0:K1]^T, operands read
+// straight from column-major FP64 storage (lda = ldb = ld).  Software
+// pipelined: the twelve loads of the next 16-wide k batch are issued before the
+// eight MFMAs of the current one.  K1 - K0 is a multiple of 4.
+__device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B, int64_t ld, int R0, int C0, int K0,
+                                               int K1, int lane, d4& acc0, d4& acc1) {
   const int r = lane & 15, q = lane >> 4;
-  int kk = 0;
-  for (; kk + 16 <= K; kk += 16) {
-    double a[4], b0[4], b1[4];
+  auto ld12 = [&](int kk, double* a, double* b0, double* b1) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t col = kk + 4 * u + q;
@@ -355,13 +356,32 @@ __device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B,
       b0[u] = B[col * ld + C0 + r];
       b1[u] = B[col * ld + C0 + 16 + r];
     }
+  };
+  int kk = K0;
+  const int full_end = K0 + ((K1 - K0) / 16) * 16;
+  if (kk < full_end) {
+    double a[4], b0[4], b1[4];
+    ld12(kk, a, b0, b1);
+    for (; kk < full_end; kk += 16) {
+      double na[4], nb0[4], nb1[4];
+      const bool more = kk + 16 < full_end;
+      if (more) ld12(kk + 16, na, nb0, nb1);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b0[u], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b1[u], acc1, 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b0[u], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b1[u], acc1, 0, 0, 0);
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = na[u];
+          b0[u] = nb0[u];
+          b1[u] = nb1[u];
+        }
+      }
     }
   }
-  for (; kk < K; kk += 4) {
+  for (; kk < K1; kk += 4) {
     const int64_t col = kk + q;
     double a = A[col * ld + R0 + r], b0 = B[col * ld + C0 + r], b1 = B[col * ld + C0 + 16 + r];
     acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
@@ -374,26 +394,69 @@ __global__ __launch_bounds__(POTRF_THREADS) void k_potrf(TileView tv, int k) {
   const int nb = tv.nb;
   double* A = (double*)tv.tile(k, k);
   __shared__ double D[PW][PW + 1];
-  __shared__ double Xs[POTRF_THREADS][PW + 1];
+  // one LDS buffer serves the per-wave partial products of the panel update
+  // (phase 1) and the per-thread rows of the panel solve (phase 3)
+  __shared__ double smem[POTRF_THREADS * (PW + 1)];
+  double(*Xs)[PW + 1] = (double(*)[PW + 1])smem;
+  double(*Ps)[16 * 33] = (double(*)[16 * 33])smem;
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = POTRF_THREADS / 64;
   if (tid == 0) fail = 0;
 
   for (int J0 = 0; J0 < nb; J0 += PW) {
-    // (1) panel update with the columns already factored
+    // (1) panel update with the columns already factored.  Work items are
+    // (16-row block, k slice); with fewer row blocks than waves the k range is
+    // split and the partial products are added through LDS in a fixed order.
     if (J0 > 0) {
       const int nrb = (nb - J0) / 16;  // 16-row blocks from J0 down
-      for (int rb = wave; rb < nrb; rb += NW) {
+      int ks = NW / nrb;               // k slices per row block
+      if (ks < 1) ks = 1;
+      while (ks > 1 && (J0 / 4) % ks) --ks;
+      const int klen = J0 / ks;        // multiple of 4
+      const int items = nrb * ks;
+      for (int it = wave; it < ((items + NW - 1) / NW) * NW; it += NW) {
+        const bool live = it < items;
+        const int rb = live ? it / ks : 0, sl = live ? it % ks : 0;
         const int R0 = J0 + rb * 16;
         d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        mfma_rows16x32(A, A, nb, R0, J0, J0, lane, acc0, acc1);
+        if (live) mfma_rows16x32(A, A, nb, R0, J0, sl * klen, (sl + 1) * klen, lane, acc0, acc1);
+        if (ks == 1) {
+          if (live) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int R = R0 + (lane >> 4) + 4 * r;
-          const int c = lane & 15;
-          if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc0[r];
-          if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= acc1[r];
+            for (int r = 0; r < 4; ++r) {
+              const int R = R0 + (lane >> 4) + 4 * r;
+              const int c = lane & 15;
+              if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc0[r];
+              if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= acc1[r];
+            }
+          }
+        } else {
+          // slices of one row block sit on consecutive waves of this round
+          double* P = Ps[wave];
+          if (live) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              P[((lane >> 4) + 4 * r) * 33 + (lane & 15)] = acc0[r];
+              P[((lane >> 4) + 4 * r) * 33 + 16 + (lane & 15)] = acc1[r];
+            }
+          }
+          __syncthreads();
+          if (live && sl == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int rr = (lane >> 4) + 4 * r, c = lane & 15;
+              const int R = R0 + rr;
+              double s0 = 0.0, s1 = 0.0;
+              for (int w2 = 0; w2 < ks; ++w2) {
+                s0 += Ps[wave + w2][rr * 33 + c];
+                s1 += Ps[wave + w2][rr * 33 + 16 + c];
+              }
+              if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= s0;
+              if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= s1;
+            }
+          }
+          __syncthreads();
         }
       }
     }
@@ -475,7 +538,7 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
   for (int J0 = 0; J0 < nb; J0 += PW) {
     // T = A[rows, J] - X[rows, :J0] L[J, :J0]^T ; wave w owns rows 16w .. 16w+15
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    mfma_rows16x32(X, Lkk, nb, r0 + wave * 16, J0, J0, lane, acc0, acc1);
+    mfma_rows16x32(X, Lkk, nb, r0 + wave * 16, J0, 0, J0, lane, acc0, acc1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int lr = wave * 16 + (lane >> 4) + 4 * r;

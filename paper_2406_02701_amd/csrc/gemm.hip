@@ -48,7 +48,15 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
 
   const S* A = (const S*)Av;
   const S* B = (const S*)Bv;
-  const int64_t r0 = (int64_t)blockIdx.x * GB, c0 = (int64_t)blockIdx.y * GB;
+  // XCD-aware order: each XCD sweeps a contiguous run of blocks, grouped 8 block
+  // rows high so that the blocks in flight on one XCD share A and B panels
+  const int gm = gridDim.x, gn = gridDim.y;
+  const int lb = xcd_remap(blockIdx.y * gm + blockIdx.x, gm * gn);
+  constexpr int GROUP = 8;
+  const int group = lb / (GROUP * gn), first = group * GROUP;
+  const int rows = (gm - first) < GROUP ? (gm - first) : GROUP;
+  const int bi = first + (lb % (GROUP * gn)) % rows, bj = (lb % (GROUP * gn)) / rows;
+  const int64_t r0 = (int64_t)bi * GB, c0 = (int64_t)bj * GB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int64_t mbA = transA ? (K + 127) / 128 : (M + 127) / 128;  // rows of A's scale grid

@@ -131,6 +131,17 @@ struct TileView {
   __device__ __forceinline__ int tfmt(int i, int j) const { return fmt[tri_index(i, j)]; }
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X (workgroup
+// b runs on XCD b % 8), each with its own L2.  This remaps the launch index so
+// that every XCD works through one contiguous range of logical blocks:
+// neighbouring blocks, which share operand panels, then share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int NXCD = 8;
+  const int xcd = bid % NXCD, idx = bid / NXCD;
+  const int per = nblocks / NXCD, rem = nblocks % NXCD;
+  return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
 struct GemmTask {
   int i, j;  // output tile (i, j); operands are tiles (i, k) and (j, k)
 };
@@ -161,6 +172,14 @@ class Arena {
   std::map<size_t, size_t> free_;            // offset -> length
   std::unordered_map<size_t, size_t> used_;  // offset -> length
 };
+
+// Internal context helpers for the serving engine (not part of the C ABI).
+int ctx_create_with_arena(int device, Arena* arena, mpcr_ctx** out);  // owns a new stream
+void ctx_release_workspace(mpcr_ctx* ctx);                            // returns cached buffers
+hipStream_t ctx_stream(mpcr_ctx* ctx);
+// Device bytes one log-likelihood evaluation of order n (tile size nb, nrhs) may hold
+// at once, for an all-FP64 map (an upper bound for any map).
+size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs);
 }  // namespace mpcr
 
 // ---------------------------------------------------------------------------

@@ -56,6 +56,11 @@ try:
 except ImportError:  # no torch: the system HIP runtime is used
     torch = None
 
+class mpcr_serve_opts_t(C.Structure):
+    _fields_ = [("nb", C.c_int64), ("band_fp64", C.c_int), ("band_fp32", C.c_int), ("far_prec", C.c_int),
+                ("guard", C.c_double), ("refine", mpcr_refine_opts_t), ("fallback_fp64", C.c_int)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build() or "
                       "python -m paper_2406_02701_amd.build)")
@@ -90,6 +95,13 @@ _SIGS = {
     "mpcr_gauss_loglik": (_i32, [_vp, _i64, _vp, _vp, _i64, _P(mpcr_theta_t), _P(mpcr_tilemap_t), _i32,
                                  _P(mpcr_refine_opts_t), _P(_d), _P(mpcr_diag_t)]),
     "mpcr_convert": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "mpcr_serve_create": (_i32, [_i32, C.c_size_t, _i32, _P(mpcr_serve_opts_t), _P(_vp)]),
+    "mpcr_serve_destroy": (_i32, [_vp]),
+    "mpcr_serve_submit": (_i32, [_vp, C.c_uint64, _i64, _P(_d), _P(_d), _P(mpcr_theta_t)]),
+    "mpcr_serve_poll": (_i32, [_vp, _P(C.c_uint64), _P(_d), _P(mpcr_diag_t), _P(_d), _P(_d), _P(_i32), _P(_i32)]),
+    "mpcr_serve_clock": (_d, [_vp]),
+    "mpcr_serve_stats": (_i32, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64), _P(C.c_size_t)]),
+    "mpcr_serve_footprint": (C.c_size_t, [_i64, _i64]),
     "mpcr_gemm": (_i32, [_vp, _i32, _i32, _i32, _i64, _i64, _i64, _d, _vp, _i64, _vp, _vp, _i64, _vp, _d, _vp,
                          _i64, _i32]),
 }
