@@ -98,13 +98,17 @@ typedef struct {
  *   max_iter     iteration cap (0 = no refinement: x = M^{-1} b)
  *   solver       0 = preconditioned conjugate gradients, 1 = classical
  *                iterative refinement x <- x + M^{-1} r
- *   recompute    PCG recomputes the true residual every `recompute` steps */
+ *   recompute    PCG recomputes the true residual every `recompute` steps
+ *   residual     mpcr_gauss_loglik only: 0 = regenerate Sigma's entries from the
+ *                sites for every residual (no extra memory); 1 = keep an FP64
+ *                copy of Sigma's lower tiles (nt(nt+1)/2 nb^2 doubles, written
+ *                with the low-precision tiles) and stream it */
 typedef struct {
   double tol;
   int max_iter;
   int solver;
   int recompute;
-  int reserved;
+  int residual;
 } mpcr_refine_opts_t;
 
 /* Diagnostics filled by mpcr_potrs / mpcr_gauss_loglik (host struct). */

@@ -92,6 +92,8 @@ struct mpcr_ctx {
   double* ws_locs = nullptr;      // n x 2 sorted sites
   double* ws_vec = nullptr;       // vector workspace
   int64_t ws_vec_bytes = 0;
+  uint8_t* ws_gemm = nullptr;     // packed 16/8-bit GEMM operands
+  int64_t ws_gemm_bytes = 0;
   hipEvent_t ev[6] = {};
   // kernel timing (see mpcr_ctx_set_profiling)
   bool profiling = false;
@@ -170,6 +172,7 @@ struct mpcr_factor {
   int* d_info = nullptr;
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles
   double* d_Linv = nullptr;        // 2 nt nb^2 doubles (inverses and their transposes)
+  double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   bool linv_ready = false;
   GemmTask* d_tasks = nullptr;
   std::vector<int64_t> task_off;   // [(k * 5 + f)] offset into d_tasks
@@ -251,7 +254,7 @@ void free_factor(mpcr_factor* f) {
   if (!f) return;
   DeviceGuard g(f->device);
   for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
-                  (void*)f->d_Linv, (void*)f->d_tasks})
+                  (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig})
     dfree(f->arena, p);
   delete f;
 }
@@ -493,6 +496,8 @@ int tile_solve(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const double* Bsrc, 
 // Sigma application for refinement: either matrix-free from sites or a dense FP64 matrix.
 struct SigmaOp {
   mpcr_ctx* ctx = nullptr;  // for kernel timing
+  const double* sig = nullptr;  // stored FP64 lower tiles (preferred when set)
+  int nb = 0, nt = 0;
   const double* locs = nullptr;
   mpcr_theta_t th{};
   const double* A = nullptr;
@@ -501,6 +506,7 @@ struct SigmaOp {
   hipError_t residual(const double* B, const double* X, double* R, int64_t ld, int nrhs, hipStream_t s,
                       double* rowsum = nullptr) const {
     auto go = [&] {
+      if (sig) return launch_residual_tiles(n, nb, nt, sig, B, X, R, ld, nrhs, s, rowsum);
       return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s, rowsum)
                : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s, rowsum);
     };
@@ -666,6 +672,9 @@ void ctx_release_workspace(mpcr_ctx* ctx) {
   dfree(ctx->arena, ctx->ws_vec);
   ctx->ws_vec = nullptr;
   ctx->ws_vec_bytes = 0;
+  dfree(ctx->arena, ctx->ws_gemm);
+  ctx->ws_gemm = nullptr;
+  ctx->ws_gemm_bytes = 0;
 }
 
 hipStream_t ctx_stream(mpcr_ctx* ctx) { return ctx->stream; }
@@ -722,6 +731,7 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     free_factor(ctx->ws_factor);
     dfree(ctx->arena, ctx->ws_locs);
     dfree(ctx->arena, ctx->ws_vec);
+    dfree(ctx->arena, ctx->ws_gemm);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     drain_timing(ctx);
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -1036,7 +1046,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
       for (int64_t j = 0; j <= i; ++j) all64 &= (m[i * nt + j] == F64);
   }
   if (opts) CHECK_ARG(ctx, opts->tol > 0 && opts->solver >= 0 && opts->solver <= 1 && opts->recompute >= 0 &&
-                               opts->max_iter >= 0,
+                               opts->max_iter >= 0 && (opts->residual == 0 || opts->residual == 1),
                       "bad refinement options");
   DeviceGuard g(ctx->device);
   hipStream_t s = ctx->stream;
@@ -1089,7 +1099,10 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     HIP_TRY(ctx, launch_copy_cols((int)n, (int)nrhs, d_Z, n, b.B, b.N, s));
   }
   HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), s));
-  HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s));
+  const bool stored_residual = opts && opts->max_iter > 0 && opts->residual == 1;
+  if (stored_residual && !f->d_sig)
+    HIP_TRY(ctx, dmalloc(f->arena, &f->d_sig, (size_t)(f->nt * (f->nt + 1) / 2) * f->nb * f->nb * 8));
+  HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s, stored_residual ? f->d_sig : nullptr));
   HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
   if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
   HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
@@ -1139,6 +1152,11 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0};
     SigmaOp op;
     op.ctx = ctx;
+    if (stored_residual) {
+      op.sig = f->d_sig;
+      op.nb = (int)f->nb;
+      op.nt = (int)f->nt;
+    }
     op.locs = locs;
     op.th = *theta;
     op.n = (int)n;
@@ -1200,8 +1218,48 @@ int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m
   CHECK_ARG(ctx, (p == F8) == (d_scaleA_exp != nullptr && d_scaleB_exp != nullptr) || k == 0,
             "FP8 operands need their scale exponents (and only FP8 takes them)");
   DeviceGuard g(ctx->device);
-  HIP_TRY(ctx, launch_gemm(prec, transA, transB, m, n, k, alpha, d_A, lda, d_scaleA_exp, d_B, ldb, d_scaleB_exp, beta,
-                           d_C, ldc, c_prec, ctx->stream));
+  hipStream_t s = ctx->stream;
+  if (p == F64 || p == F32) {
+    HIP_TRY(ctx, launch_gemm(p, transA, transB, m, n, k, alpha, d_A, lda, d_B, ldb, beta, d_C, ldc, cp, s));
+    return MPCR_OK;
+  }
+  // 16/8-bit: the kernel reads op(A) as m x k and op(B) as n x k arrays with k
+  // contiguous and 16-byte aligned rows; operands in another layout are packed
+  // into a workspace first (one pass over each, small next to the product).
+  const int es = (p == F8) ? 1 : 2;
+  auto usable = [&](const void* ptr, int64_t ld, bool kcontig) {
+    return kcontig && ((uintptr_t)ptr % 16 == 0) && ((ld * es) % 16 == 0);
+  };
+  const bool a_ok = usable(d_A, lda, transA != 0), b_ok = usable(d_B, ldb, transB == 0);
+  const int64_t ldk = (k + 15) / 16 * 16;  // packed leading dimension (elements)
+  const int64_t a_bytes = a_ok ? 0 : (m * ldk * es + 255) / 256 * 256, b_bytes = b_ok ? 0 : n * ldk * es;
+  if (ctx->ws_gemm_bytes < a_bytes + b_bytes) {
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    dfree(ctx->arena, ctx->ws_gemm);
+    ctx->ws_gemm = nullptr;
+    ctx->ws_gemm_bytes = 0;
+    HIP_TRY(ctx, dmalloc(ctx->arena, &ctx->ws_gemm, (size_t)(a_bytes + b_bytes)));
+    ctx->ws_gemm_bytes = a_bytes + b_bytes;
+  }
+  const void* A = d_A;
+  int64_t ldat = lda;
+  if (!a_ok) {
+    A = ctx->ws_gemm;
+    ldat = ldk;
+    HIP_TRY(ctx, launch_pack(es, transA == 0, m, k, d_A, lda, ctx->ws_gemm, ldk, s));
+  }
+  const void* B = d_B;
+  int64_t ldbk = ldb;
+  if (!b_ok) {
+    B = ctx->ws_gemm + a_bytes;
+    ldbk = ldk;
+    HIP_TRY(ctx, launch_pack(es, transB != 0, n, k, d_B, ldb, ctx->ws_gemm + a_bytes, ldk, s));
+  }
+  // FP8 scale grids belong to the stored matrices (column-major over 128 x 128 blocks)
+  const int64_t mbA = transA ? (k + 127) / 128 : (m + 127) / 128;
+  const int64_t mbB = transB ? (n + 127) / 128 : (k + 127) / 128;
+  HIP_TRY(ctx, launch_gemm_lowp(p, m, n, k, alpha, A, ldat, d_scaleA_exp, mbA, transA != 0, B, ldbk, d_scaleB_exp,
+                                mbB, transB != 0, beta, d_C, ldc, cp, s));
   return MPCR_OK;
 }
 

@@ -12,6 +12,8 @@
 // One workgroup computes a 128 x 128 block of C with four waves (2 x 2), each
 // 64 x 64 = 4 x 4 MFMA tiles; operands are staged through LDS, k-major for the
 // FP64/FP32 paths and row-major (k contiguous per row) for the 16/8-bit paths.
+// The FP8 k blocks of 128 are those of the block scaling (one exponent per
+// 128 x 128 block of each operand).
 #include "mpcr_internal.h"
 
 namespace mpcr {
@@ -25,26 +27,19 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 constexpr int GB = 128;  // block of C per workgroup
 
 template <int P> struct GTraits;
-template <> struct GTraits<F64> { using S = double; static constexpr int BK = 16; static constexpr bool KM = true; };
-template <> struct GTraits<F32> { using S = float; static constexpr int BK = 32; static constexpr bool KM = true; };
-template <> struct GTraits<BF16> { using S = uint16_t; static constexpr int BK = 64; static constexpr bool KM = false; };
-template <> struct GTraits<F16> { using S = uint16_t; static constexpr int BK = 64; static constexpr bool KM = false; };
-template <> struct GTraits<F8> { using S = uint8_t; static constexpr int BK = 64; static constexpr bool KM = false; };
+template <> struct GTraits<F64> { using S = double; static constexpr int BK = 16; };
+template <> struct GTraits<F32> { using S = float; static constexpr int BK = 32; };
 
+// FP64 / FP32 path: operands staged k-major ([BK][GB + pad]) through LDS.
 template <int P>
 __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
-                                              const void* Av, int64_t lda, const int8_t* sA, const void* Bv,
-                                              int64_t ldb, const int8_t* sB, double beta, void* Cv, int64_t ldc,
-                                              int cprec) {
+                                              const void* Av, int64_t lda, const void* Bv, int64_t ldb, double beta,
+                                              void* Cv, int64_t ldc, int cprec) {
   using S = typename GTraits<P>::S;
   constexpr int BK = GTraits<P>::BK;
-  constexpr bool KM = GTraits<P>::KM;
-  constexpr int PADK = (sizeof(S) >= 4) ? (16 / (int)sizeof(S)) : 16 / (int)sizeof(S);
-  // k-major: [BK][GB + pad]; row-major: [GB][BK + pad]
-  constexpr int D0 = KM ? BK : GB;
-  constexpr int D1 = KM ? GB + PADK : BK + PADK;
-  __shared__ __attribute__((aligned(16))) S As[D0][D1];
-  __shared__ __attribute__((aligned(16))) S Bs[D0][D1];
+  constexpr int PADK = 16 / (int)sizeof(S);
+  __shared__ __attribute__((aligned(16))) S As[BK][GB + PADK];
+  __shared__ __attribute__((aligned(16))) S Bs[BK][GB + PADK];
 
   const S* A = (const S*)Av;
   const S* B = (const S*)Bv;
@@ -59,8 +54,6 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
   const int64_t r0 = (int64_t)bi * GB, c0 = (int64_t)bj * GB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int64_t mbA = transA ? (K + 127) / 128 : (M + 127) / 128;  // rows of A's scale grid
-  const int64_t mbB = transB ? (N + 127) / 128 : (K + 127) / 128;
 
   constexpr int PER = GB * BK / 256;  // elements per thread per operand
   S ra[PER], rb[PER];
@@ -86,16 +79,15 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
       const int e = tid + 256 * q;
       int r, kk;
       if (!transA) { r = e % GB; kk = e / GB; } else { kk = e % BK; r = e / BK; }
-      if (KM) As[kk][r] = ra[q]; else As[r][kk] = ra[q];
+      As[kk][r] = ra[q];
       int c, kb;
       if (transB) { c = e % GB; kb = e / GB; } else { kb = e % BK; c = e / BK; }
-      if (KM) Bs[kb][c] = rb[q]; else Bs[c][kb] = rb[q];
+      Bs[kb][c] = rb[q];
     }
   };
 
   using Acc = typename std::conditional<P == F64, d4, f4>::type;
   Acc acc[4][4];
-  f4 part[4][4];  // FP8 only: sums of the current 128-wide k block
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -107,7 +99,7 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
     sstore();
     __syncthreads();
     if (k0 + BK < K) gload(k0 + BK);
-    if constexpr (P == F64 || P == F32) {
+    {
 #pragma unroll
       for (int k4 = 0; k4 < BK; k4 += 4) {
         S av[4], bv[4];
@@ -124,56 +116,6 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
             else
               acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
           }
-      }
-    } else if constexpr (P == BF16 || P == F16) {
-#pragma unroll
-      for (int k32 = 0; k32 < BK; k32 += 32) {
-        u16x8 av[4], bv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = *(const u16x8*)&As[wm * 64 + a * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = *(const u16x8*)&Bs[wn * 64 + b * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            if constexpr (P == BF16)
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[a]),
-                                                                   __builtin_bit_cast(bf16x8, bv[b]), acc[a][b], 0, 0, 0);
-            else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av[a]),
-                                                                  __builtin_bit_cast(f16x8, bv[b]), acc[a][b], 0, 0, 0);
-          }
-      }
-    } else {  // FP8: the two 64-wide slabs of each 128-wide k block share one scale
-      if (k0 % 128 == 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) part[a][b] = f4{0, 0, 0, 0};
-      }
-#pragma unroll
-      for (int k32 = 0; k32 < BK; k32 += 32) {
-        long av[4], bv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = *(const long*)&As[wm * 64 + a * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = *(const long*)&Bs[wn * 64 + b * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            part[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[b], part[a][b], 0, 0, 0);
-      }
-      if (k0 % 128 == 64 || k0 + BK >= K) {
-        const int64_t kb = k0 / 128, ib = r0 / 128, jb = c0 / 128;
-        const int ea = transA ? sA[ib * mbA + kb] : sA[kb * mbA + ib];
-        const int eb = transB ? sB[kb * mbB + jb] : sB[jb * mbB + kb];
-        const float sc = ldexpf(1.0f, -(ea + eb));
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] += sc * part[a][b];
       }
     }
   }
@@ -202,16 +144,226 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
       }
 }
 
-hipError_t launch_gemm(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const void* A,
-                       int64_t lda, const int8_t* sA, const void* B, int64_t ldb, const int8_t* sB, double beta,
-                       void* C, int64_t ldc, int cprec, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// 16- and 8-bit path.  Both operands are read "k-contiguous": A as an m x k
+// row-major array (AT, leading dimension ldat) and B as the usual k x n
+// column-major array.  Every thread moves 16-byte vectors global -> LDS, rows
+// are padded by 16 bytes (conflict-free 16-byte fragment reads), LDS is
+// double-buffered.  Operands in another layout, or whose rows are not 16-byte
+// aligned, are first packed (k_pack).  FP8 takes one 128-wide k block per
+// chunk, so each chunk's sums are scaled by 2^-(sA + sB) once.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_gemm_lowp(int64_t M, int64_t N, int64_t K, double alpha, const void* ATv,
+                                                   int64_t ldat, const int8_t* sA, int64_t mbA, const void* Bv,
+                                                   int64_t ldb, const int8_t* sB, int64_t mbB, int sa_kmajor,
+                                                   int sb_kmajor, double beta, void* Cv, int64_t ldc, int cprec) {
+  constexpr int ES = (P == F8) ? 1 : 2;       // element bytes
+  constexpr int BK = (P == F8) ? 128 : 64;    // k per chunk (one FP8 scale block)
+  constexpr int VE = 16 / ES;                 // elements per 16-byte vector
+  constexpr int LDR = BK * ES + 16;           // padded LDS row in bytes
+  constexpr int VPR = BK / VE;                // vectors per row per chunk (8)
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][GB * LDR];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][GB * LDR];
+
+  const uint8_t* AT = (const uint8_t*)ATv;
+  const uint8_t* B = (const uint8_t*)Bv;
+  const int gm = gridDim.x, gn = gridDim.y;
+  const int lb = xcd_remap(blockIdx.y * gm + blockIdx.x, gm * gn);
+  constexpr int GROUP = 8;
+  const int group = lb / (GROUP * gn), first = group * GROUP;
+  const int rows = (gm - first) < GROUP ? (gm - first) : GROUP;
+  const int bi = first + (lb % (GROUP * gn)) % rows, bj = (lb % (GROUP * gn)) / rows;
+  const int64_t r0 = (int64_t)bi * GB, c0 = (int64_t)bj * GB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const bool full = (r0 + GB <= M) && (c0 + GB <= N) && (K % BK == 0);
+
+  // loader: thread t moves vectors (row = t / VPR + 32 v, chunk t % VPR), v = 0..3
+  uint4 ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tid / VPR + 32 * v, kc = tid % VPR;
+      const int64_t gk = k0 + kc * VE;
+      const int64_t ga = r0 + row, gb = c0 + row;
+      if (full || (ga < M && gk + VE <= K)) {
+        ra[v] = *(const uint4*)(AT + (ga * ldat + gk) * ES);
+      } else {
+        uint8_t tmp[16] = {0};
+        for (int e = 0; e < VE; ++e)
+          if (ga < M && gk + e < K)
+            for (int b = 0; b < ES; ++b) tmp[e * ES + b] = AT[(ga * ldat + gk + e) * ES + b];
+        ra[v] = *(uint4*)tmp;
+      }
+      if (full || (gb < N && gk + VE <= K)) {
+        rb[v] = *(const uint4*)(B + (gb * ldb + gk) * ES);
+      } else {
+        uint8_t tmp[16] = {0};
+        for (int e = 0; e < VE; ++e)
+          if (gb < N && gk + e < K)
+            for (int b = 0; b < ES; ++b) tmp[e * ES + b] = B[(gb * ldb + gk + e) * ES + b];
+        rb[v] = *(uint4*)tmp;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tid / VPR + 32 * v, kc = tid % VPR;
+      *(uint4*)&As[buf][row * LDR + kc * 16] = ra[v];
+      *(uint4*)&Bs[buf][row * LDR + kc * 16] = rb[v];
+    }
+  };
+
+  f4 acc[4][4], part[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+  if (K > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) gload(k0 + BK);
+    if constexpr (P == F8) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) part[a][b] = f4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int k32 = 0; k32 < BK; k32 += 32) {
+      const int kb = (k32 + 8 * (lane >> 4)) * ES;  // byte offset of this lane's 8 k values
+      if constexpr (P == F8) {
+        long av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = *(const long*)&As[cur][(wm * 64 + a * 16 + (lane & 15)) * LDR + kb];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = *(const long*)&Bs[cur][(wn * 64 + b * 16 + (lane & 15)) * LDR + kb];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            part[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[b], part[a][b], 0, 0, 0);
+      } else {
+        u16x8 av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = *(const u16x8*)&As[cur][(wm * 64 + a * 16 + (lane & 15)) * LDR + kb];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = *(const u16x8*)&Bs[cur][(wn * 64 + b * 16 + (lane & 15)) * LDR + kb];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            if constexpr (P == BF16)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[a]),
+                                                                   __builtin_bit_cast(bf16x8, bv[b]), acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av[a]),
+                                                                  __builtin_bit_cast(f16x8, bv[b]), acc[a][b], 0, 0, 0);
+          }
+      }
+    }
+    if constexpr (P == F8) {
+      const int64_t kb = k0 / 128, ib = r0 / 128, jb = c0 / 128;
+      const int ea = sa_kmajor ? sA[ib * mbA + kb] : sA[kb * mbA + ib];
+      const int eb = sb_kmajor ? sB[kb * mbB + jb] : sB[jb * mbB + kb];
+      const float sc = ldexpf(1.0f, -(ea + eb));
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += sc * part[a][b];
+    }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = r0 + wm * 64 + a * 16 + 4 * (lane >> 4) + r;
+        const int64_t Cc = c0 + wn * 64 + b * 16 + (lane & 15);
+        if (R >= M || Cc >= N) continue;
+        const int64_t idx = Cc * ldc + R;
+        double v = alpha * (double)acc[a][b][r];
+        if (cprec == F64) {
+          double* Cp = (double*)Cv;
+          if (beta != 0.0) v += beta * Cp[idx];
+          Cp[idx] = v;
+        } else {
+          float* Cp = (float*)Cv;
+          if (beta != 0.0) v += beta * (double)Cp[idx];
+          Cp[idx] = (float)v;
+        }
+      }
+}
+
+// Packs a rows x cols operand into a k-contiguous array: out[r * ldo + c] =
+// element (r, c), read from in[c * ldi + r] (TR) or in[r * ldi + c] (!TR).
+// 64 x 64 pieces go through LDS so that both the reads and the writes are
+// coalesced.
+template <typename T, bool TR>
+__global__ __launch_bounds__(256) void k_pack(int64_t rows, int64_t cols, const T* in, int64_t ldi, T* out,
+                                              int64_t ldo) {
+  __shared__ T t[64][65];
+  const int64_t rb = (int64_t)blockIdx.x * 64, cb = (int64_t)blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int fast = e % 64, slow = e / 64;
+    const int r = TR ? fast : slow, c = TR ? slow : fast;
+    if (rb + r < rows && cb + c < cols) t[r][c] = TR ? in[(cb + c) * ldi + rb + r] : in[(rb + r) * ldi + cb + c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int c = e % 64, r = e / 64;
+    if (rb + r < rows && cb + c < cols) out[(rb + r) * ldo + cb + c] = t[r][c];
+  }
+}
+
+hipError_t launch_pack(int es, int trans, int64_t rows, int64_t cols, const void* in, int64_t ldi, void* out,
+                       int64_t ldo, hipStream_t s) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+  if (es == 1) {
+    if (trans) k_pack<uint8_t, true><<<grid, 256, 0, s>>>(rows, cols, (const uint8_t*)in, ldi, (uint8_t*)out, ldo);
+    else k_pack<uint8_t, false><<<grid, 256, 0, s>>>(rows, cols, (const uint8_t*)in, ldi, (uint8_t*)out, ldo);
+  } else {
+    if (trans) k_pack<uint16_t, true><<<grid, 256, 0, s>>>(rows, cols, (const uint16_t*)in, ldi, (uint16_t*)out, ldo);
+    else k_pack<uint16_t, false><<<grid, 256, 0, s>>>(rows, cols, (const uint16_t*)in, ldi, (uint16_t*)out, ldo);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_lowp(int prec, int64_t m, int64_t n, int64_t k, double alpha, const void* AT, int64_t ldat,
+                            const int8_t* sA, int64_t mbA, int sa_kmajor, const void* B, int64_t ldb,
+                            const int8_t* sB, int64_t mbB, int sb_kmajor, double beta, void* C, int64_t ldc, int cprec,
+                            hipStream_t s) {
   dim3 grid((unsigned)((m + GB - 1) / GB), (unsigned)((n + GB - 1) / GB));
   switch (prec) {
-    case F64: k_gemm<F64><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, cprec); break;
-    case F32: k_gemm<F32><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, cprec); break;
-    case BF16: k_gemm<BF16><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, cprec); break;
-    case F16: k_gemm<F16><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, cprec); break;
-    case F8: k_gemm<F8><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, cprec); break;
+    case BF16: k_gemm_lowp<BF16><<<grid, 256, 0, s>>>(m, n, k, alpha, AT, ldat, sA, mbA, B, ldb, sB, mbB, sa_kmajor, sb_kmajor, beta, C, ldc, cprec); break;
+    case F16: k_gemm_lowp<F16><<<grid, 256, 0, s>>>(m, n, k, alpha, AT, ldat, sA, mbA, B, ldb, sB, mbB, sa_kmajor, sb_kmajor, beta, C, ldc, cprec); break;
+    case F8: k_gemm_lowp<F8><<<grid, 256, 0, s>>>(m, n, k, alpha, AT, ldat, sA, mbA, B, ldb, sB, mbB, sa_kmajor, sb_kmajor, beta, C, ldc, cprec); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const void* A,
+                       int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc, int cprec,
+                       hipStream_t s) {
+  dim3 grid((unsigned)((m + GB - 1) / GB), (unsigned)((n + GB - 1) / GB));
+  switch (prec) {
+    case F64: k_gemm<F64><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cprec); break;
+    case F32: k_gemm<F32><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cprec); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -188,8 +188,9 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs);
 namespace mpcr {
 
 hipError_t launch_tiles_from_dense(const TileView& tv, const double* A, int64_t lda, hipStream_t s);
+// sig64 != NULL: also write each tile's FP64 values (packed tile order, nb^2 doubles per tile)
 hipError_t launch_tiles_from_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
-                                        hipStream_t s);
+                                        hipStream_t s, double* sig64 = nullptr);
 hipError_t launch_tiles_to_dense(const TileView& tv, double* L, int64_t ldl, hipStream_t s);
 hipError_t launch_covariance_dense(int n, const double* locs, const mpcr_theta_t& th, double* A,
                                    int64_t lda, hipStream_t s);
@@ -219,6 +220,10 @@ hipError_t launch_residual_cov(int n, const double* locs, const mpcr_theta_t& th
                                const double* X, double* R, int64_t ld, int nrhs, hipStream_t s,
                                double* rowsum = nullptr);
 hipError_t launch_residual_dense(int n, const double* A, int64_t lda, const double* B, const double* X,
+                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum = nullptr);
+// R = B - Sigma X from the FP64 copy of Sigma's lower tiles (B == NULL: R = -Sigma X);
+// rowsum != NULL also receives sum_c |Sigma_rc|
+hipError_t launch_residual_tiles(int n, int nb, int nt, const double* sig64, const double* B, const double* X,
                                  double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum = nullptr);
 hipError_t launch_rowsum_abs_cov(int n, const double* locs, const mpcr_theta_t& th, double* out,
                                  hipStream_t s);
@@ -254,7 +259,13 @@ hipError_t launch_gather_rows(int n, int ncols, const double* src, int64_t lds, 
                               double* dst, int64_t ldd, hipStream_t s);
 
 hipError_t launch_gemm(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha,
-                       const void* A, int64_t lda, const int8_t* sA, const void* B, int64_t ldb,
-                       const int8_t* sB, double beta, void* C, int64_t ldc, int cprec, hipStream_t s);
+                       const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                       int cprec, hipStream_t s);
+hipError_t launch_pack(int es, int trans, int64_t rows, int64_t cols, const void* in, int64_t ldi, void* out,
+                       int64_t ldo, hipStream_t s);
+hipError_t launch_gemm_lowp(int prec, int64_t m, int64_t n, int64_t k, double alpha, const void* AT, int64_t ldat,
+                            const int8_t* sA, int64_t mbA, int sa_kmajor, const void* B, int64_t ldb,
+                            const int8_t* sB, int64_t mbB, int sb_kmajor, double beta, void* C, int64_t ldc, int cprec,
+                            hipStream_t s);
 
 }  // namespace mpcr

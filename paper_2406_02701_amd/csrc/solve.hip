@@ -50,12 +50,22 @@ __device__ void gemv_n_rows(const void* M, int nb, int r0, const double* V, int6
 #pragma unroll
     for (int j = 0; j < RHS_CHUNK; ++j) acc[j] = 0.0;
     const int64_t base = (int64_t)r0 + r;
-#pragma unroll 8
-    for (int k = kb; k < kb + kq; ++k) {
-      const double m = ldw<F>(M, (int64_t)k * nb + base);
-      const double* vk = Vs + k * RHS_CHUNK;
+    // 32 independent loads per batch keep enough requests in flight to cover
+    // the memory latency at one wave per SIMD
+    constexpr int BATCH = 32;
+    for (int k0 = kb; k0 < kb + kq; k0 += BATCH) {
+      const int kn = (kb + kq - k0) < BATCH ? (kb + kq - k0) : BATCH;
+      double mv[BATCH];
 #pragma unroll
-      for (int j = 0; j < RHS_CHUNK; ++j) acc[j] += m * vk[j];
+      for (int u = 0; u < BATCH; ++u) mv[u] = u < kn ? ldw<F>(M, (int64_t)(k0 + u) * nb + base) : 0.0;
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const double* vk = Vs + (k0 + u) * RHS_CHUNK;
+        if (u < kn) {
+#pragma unroll
+          for (int j = 0; j < RHS_CHUNK; ++j) acc[j] += mv[u] * vk[j];
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -344,6 +354,74 @@ hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* 
   if (n == 0) return hipSuccess;
   k_sigma_apply<1, true><<<(n + 63) / 64, 256, 0, s>>>(n, nullptr, 0, 1, 0, 0, A, lda, nullptr, nullptr, out, 0, 1,
                                                        nullptr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual from the stored lower tiles of Sigma: row block (i, r0 .. r0+63)
+// of Sigma X is sum_{j <= i} S_ij X_j + sum_{j > i} S_ji^T X_j.  Every
+// workgroup streams one block row of Sigma in 64 x 64 pieces through LDS (the
+// transposed pieces are loaded column-wise, so all loads are contiguous) and
+// sums in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_residual_tiles(int n, int nb, int nt, const double* sig, const double* B,
+                                                        const double* X, double* R, int64_t ld, int nrhs,
+                                                        double* rowsum) {
+  __shared__ double S[64][65];
+  __shared__ double Xc[64][RHS_CHUNK];
+  const int tid = threadIdx.x;
+  const int rb = nb / 64;
+  const int i = blockIdx.x / rb, r0 = (blockIdx.x % rb) * 64;
+  const int rr = tid & 63, q = tid >> 6;        // compute: row rr, right-hand sides 4q .. 4q+3
+  const int lr = tid >> 2, lc = (tid & 3) * 16;  // load: 16 consecutive elements of one column
+  const int64_t t2 = (int64_t)nb * nb;
+  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
+    double acc[4] = {0, 0, 0, 0}, asum = 0.0;
+    for (int j = 0; j < nt; ++j) {
+      const bool low = j <= i;
+      const double* T = sig + tri_index(low ? i : j, low ? j : i) * t2;
+      for (int k0 = 0; k0 < nb; k0 += 64) {
+        __syncthreads();
+        for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
+          const int c = e / 64, k = e % 64;
+          Xc[k][c] = c < nc ? X[(int64_t)(c0 + c) * ld + (int64_t)j * nb + k0 + k] : 0.0;
+        }
+        if (low) {  // S[r][c] = T[k0 + c][r0 + r]: column k0+lr, rows r0+lc ..
+          const double* src = T + (int64_t)(k0 + lr) * nb + r0 + lc;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) S[lc + e][lr] = src[e];
+        } else {    // S[r][c] = T[r0 + r][k0 + c]^T = T(col r0 + r, row k0 + c)
+          const double* src = T + (int64_t)(r0 + lr) * nb + k0 + lc;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) S[lr][lc + e] = src[e];
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int k = 0; k < 64; ++k) {
+          const double m = S[rr][k];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) acc[jj] += m * Xc[k][4 * q + jj];
+          if (rowsum && c0 == 0 && q == 0) asum += fabs(m);
+        }
+      }
+    }
+    const int grow = i * nb + r0 + rr;
+    if (grow < n) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int c = 4 * q + jj;
+        if (c < nc) R[(int64_t)(c0 + c) * ld + grow] = (B ? B[(int64_t)(c0 + c) * ld + grow] : 0.0) - acc[jj];
+      }
+      if (rowsum && c0 == 0 && q == 0) rowsum[grow] = asum;
+    }
+  }
+}
+
+hipError_t launch_residual_tiles(int n, int nb, int nt, const double* sig64, const double* B, const double* X,
+                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum) {
+  if (n == 0) return hipSuccess;
+  k_residual_tiles<<<nt * (nb / 64), 256, 0, s>>>(n, nb, nt, sig64, B, X, R, ld, nrhs, rowsum);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ __device__ __forceinline__ void tri_unpack(int t, int& i, int& j) {
 // stores into the column-major tile are contiguous.
 template <int MODE>  // 0: from covariance, 1: from dense FP64 lower triangle
 __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* src, int64_t lds, double s2,
-                                                   double range, int nuc, double nugget) {
+                                                   double range, int nuc, double nugget, double* sig64) {
   int ti, tj;
   tri_unpack(blockIdx.x, ti, tj);
   const int nb = tv.nb, n = tv.n;
@@ -61,19 +61,20 @@ __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* s
       v = src[(int64_t)lo * lds + hi];
     }
     store_round(tile, f, (int64_t)c * nb + r, v);
+    if (sig64) sig64[(int64_t)blockIdx.x * nb * nb + (int64_t)c * nb + r] = v;  // FP64 copy, packed tile order
   }
 }
 
 hipError_t launch_tiles_from_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
-                                        hipStream_t s) {
+                                        hipStream_t s, double* sig64) {
   dim3 grid(tv.nt * (tv.nt + 1) / 2, tv.nb / 16);
-  k_fill_tiles<0><<<grid, 256, 0, s>>>(tv, locs, 0, th.sigma2, th.range, nu_code(th.nu), th.nugget);
+  k_fill_tiles<0><<<grid, 256, 0, s>>>(tv, locs, 0, th.sigma2, th.range, nu_code(th.nu), th.nugget, sig64);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles_from_dense(const TileView& tv, const double* A, int64_t lda, hipStream_t s) {
   dim3 grid(tv.nt * (tv.nt + 1) / 2, tv.nb / 16);
-  k_fill_tiles<1><<<grid, 256, 0, s>>>(tv, A, lda, 0, 1, 0, 0);
+  k_fill_tiles<1><<<grid, 256, 0, s>>>(tv, A, lda, 0, 1, 0, 0, nullptr);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ class mpcr_theta_t(C.Structure):
 
 class mpcr_refine_opts_t(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("solver", C.c_int), ("recompute", C.c_int),
-                ("reserved", C.c_int)]
+                ("residual", C.c_int)]
 
 
 class mpcr_diag_t(C.Structure):

@@ -127,3 +127,26 @@ def test_gemm_full_size_sampled(g, fmt):
     err = np.max(np.abs(got[rows, cols] - ref))
     assert err <= 4 * N * u_acc(fmt) * scale, err
     assert got.shape == (N, N) and np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp8_e4m3"])
+def test_gemm_k_contiguous_operands_read_in_place(g, fmt):
+    """op(A) = A^T and B untransposed with 16-byte aligned leading dimensions
+    larger than the rows (k = 376, ld = 384): the 16/8-bit kernel reads both
+    operands in place, including the ragged last k chunk."""
+    from paper_2406_02701_amd import mpcr
+    gu, ctx = g
+    m, n, k, ld = 300, 200, 376, 384
+    A = np.zeros((ld, m))
+    A[:k] = synth.uniform_matrix(k, m, 107)     # stored k x m, op(A) = A^T
+    B = np.zeros((ld, n))
+    B[:k] = synth.uniform_matrix(k, n, 108)
+    dA, sA = convert(gu, ctx, A, fmt)
+    dB, sB = convert(gu, ctx, B, fmt)
+    dC = gu.empty(m, n, torch.float32)
+    ctx.check(mpcr.mpcr_gemm(ctx.ptr, mpcr.PREC[fmt], 1, 0, m, n, k, 1.0, dA.data_ptr(), ld,
+                             None if sA is None else sA.data_ptr(), dB.data_ptr(), ld,
+                             None if sB is None else sB.data_ptr(), 0.0, dC.data_ptr(), m, mpcr.PREC["fp32"]))
+    got = gu.host(dC, (m, n)).astype(np.float64)
+    ref = og.gemm_emulated(A[:k], B[:k], fmt, transA=True, c_fmt="fp32")
+    assert og.rel_frobenius(got, ref) <= 4 * math.sqrt(k) * u_acc(fmt)

@@ -333,3 +333,26 @@ def test_literal_bf16_band_map_breaks_down(g):
     st, ll, diag = _loglik(gu, ctx, locs, z, th, nb, m, order=1, opts=mpcr.mpcr_refine_opts_t(1e-9, 50, 0, 20, 0))
     assert st == mpcr.MPCR_ERR_NOT_SPD
     assert 1 <= diag.info <= n
+
+
+def test_stored_and_matrix_free_residuals_agree(g):
+    """Refinement with the FP64 residual streamed from a stored copy of Sigma's
+    tiles reaches the same log-likelihood as regenerating Sigma from the sites."""
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    n, nb = 1800, 128
+    locs = synth.locations(n, 93)
+    z = synth.normal_rhs(n, 3, 94)
+    th = gu.theta(1.0, 0.05, 2.5, 1e-5)
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (None, "fp32")))
+    out = []
+    for mode in (0, 1):
+        opts = mpcr.mpcr_refine_opts_t(1e-13, 100, 0, 20, mode)
+        st, ll, diag = _loglik(gu, ctx, locs, z, th, nb, m, order=1, opts=opts)
+        ctx.check(st)
+        assert diag.converged == 1 and diag.eta <= 1e-13
+        out.append((ll, diag))
+    np.testing.assert_allclose(out[0][0], out[1][0], rtol=1e-11)
+    lo, zo, _ = loglik.order_sites(locs, z)
+    ref = loglik.loglik_plain(lo, zo, 1.0, 0.05, 2.5, 1e-5)
+    np.testing.assert_allclose(out[1][1].quad0, ref["quad"][0], rtol=1e-8)
