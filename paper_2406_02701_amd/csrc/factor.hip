@@ -98,51 +98,36 @@ __device__ __forceinline__ void rmw_sub(void* Cp, int64_t idx, double acc) {
 }
 
 // FP64 / FP32: operands staged k-major in LDS ([k][m]), double-buffered;
-// fragments are contiguous across lanes.  The source format of each operand is
-// dispatched once per k chunk, not per element.
-template <int CF>
-__global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
+// fragments are contiguous across lanes.  The main loop is instantiated per
+// pair of operand formats (one branch per workgroup), so each variant holds
+// only its own staging registers.
+template <int CF> struct KMajor {
   using T = typename CTraits<CF>::T;
-  constexpr int BK = (CF == F64) ? 16 : 32;
-  constexpr int PAD = (CF == F64) ? 2 : 4;
-  constexpr int G = BK / 8;  // 4-row groups per thread per operand
-  __shared__ __attribute__((aligned(16))) T As[2][BK][UBM + PAD];
-  __shared__ __attribute__((aligned(16))) T Bs[2][BK][UBM + PAD];
+  static constexpr int BK = (CF == F64) ? 16 : 32;
+  static constexpr int PAD = (CF == F64) ? 2 : 4;
+  static constexpr int G = BK / 8;  // 4-row groups per thread per operand
+  using Acc = typename std::conditional<CF == F64, d4, f4>::type;
+  using Buf = T[2][BK][UBM + PAD];
+};
 
-  const int nb = tv.nb;
-  const int sub = nb / UBM;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int task = lb / (sub * sub);
-  const int blk = lb % (sub * sub);
-  const int bm = blk % sub, bn = blk / sub;
-  const GemmTask t = tasks[task];
-  if (t.i == t.j && bn > bm) return;
-  if (*tv.info) return;
-
-  const void* Ap = tv.tile(t.i, k);
-  const void* Bp = tv.tile(t.j, k);
-  const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
+template <int CF, int FA, int FB>
+__device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, int nb, int64_t arow0, int64_t brow0,
+                                                typename KMajor<CF>::Buf& As, typename KMajor<CF>::Buf& Bs,
+                                                typename KMajor<CF>::Acc (&acc)[4][4]) {
+  using K = KMajor<CF>;
+  using T = typename K::T;
+  constexpr int BK = K::BK, G = K::G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int lr = (tid & 31) * 4;  // loader rows lr .. lr+3
   const int lc = tid >> 5;        // loader column (+ 8 g)
-  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
-
   T ra[G][4], rb[G][4];
-  auto gload_op = [&](const void* P, int f, int64_t row0, int kk, T (*dst)[4]) {
-#define MPCR_LOAD_CASE(SF)                                                    \
-  case SF:                                                                    \
-    _Pragma("unroll") for (int g = 0; g < G; ++g)                             \
-      load4<CF, SF>(P, (int64_t)(kk + lc + 8 * g) * nb + row0 + lr, dst[g]);  \
-    break;
-    switch (f) {
-      MPCR_LOAD_CASE(F64)
-      MPCR_LOAD_CASE(F32)
-      MPCR_LOAD_CASE(F16)
-      MPCR_LOAD_CASE(BF16)
-      MPCR_LOAD_CASE(F8)
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      load4<CF, FA>(Ap, (int64_t)(kk + lc + 8 * g) * nb + arow0 + lr, ra[g]);
+      load4<CF, FB>(Bp, (int64_t)(kk + lc + 8 * g) * nb + brow0 + lr, rb[g]);
     }
-#undef MPCR_LOAD_CASE
   };
   auto sstore = [&](int buf) {
 #pragma unroll
@@ -153,25 +138,13 @@ __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const
         Bs[buf][lc + 8 * g][lr + r] = rb[g][r];
       }
   };
-
-  using Acc = typename std::conditional<CF == F64, d4, f4>::type;
-  Acc acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
-
-  gload_op(Ap, fa, arow0, 0, ra);
-  gload_op(Bp, fb, brow0, 0, rb);
+  gload(0);
   sstore(0);
   __syncthreads();
   int cur = 0;
   for (int kk = 0; kk < nb; kk += BK) {
     const bool more = kk + BK < nb;
-    if (more) {
-      gload_op(Ap, fa, arow0, kk + BK, ra);
-      gload_op(Bp, fb, brow0, kk + BK, rb);
-    }
+    if (more) gload(kk + BK);
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
       T av[4], bv[4];
@@ -193,6 +166,51 @@ __global__ __launch_bounds__(256) void k_update_kmajor(TileView tv, int k, const
     __syncthreads();
     cur ^= 1;
   }
+}
+
+template <int CF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update_kmajor(TileView tv, int k,
+                                                                                            const GemmTask* tasks) {
+  using K = KMajor<CF>;
+  __shared__ __attribute__((aligned(16))) typename K::Buf As;
+  __shared__ __attribute__((aligned(16))) typename K::Buf Bs;
+
+  const int nb = tv.nb;
+  const int sub = nb / UBM;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int task = lb / (sub * sub);
+  const int blk = lb % (sub * sub);
+  const int bm = blk % sub, bn = blk / sub;
+  const GemmTask t = tasks[task];
+  if (t.i == t.j && bn > bm) return;
+  if (*tv.info) return;
+
+  const void* Ap = tv.tile(t.i, k);
+  const void* Bp = tv.tile(t.j, k);
+  const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
+
+  typename K::Acc acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = typename K::Acc{0, 0, 0, 0};
+
+  // tile formats are F64, F32, F16 or BF16 (codes 0..3)
+#define MPCR_PAIR(FA, FB) \
+  case FA * 4 + FB: kmajor_mainloop<CF, FA, FB>(Ap, Bp, nb, arow0, brow0, As, Bs, acc); break;
+#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16)
+  switch (fa * 4 + fb) {
+    MPCR_ROW(F64)
+    MPCR_ROW(F32)
+    MPCR_ROW(F16)
+    MPCR_ROW(BF16)
+    default: break;
+  }
+#undef MPCR_ROW
+#undef MPCR_PAIR
 
   void* Cp = tv.tile(t.i, t.j);
   const int fc = tv.tfmt(t.i, t.j);
@@ -511,8 +529,192 @@ __global__ __launch_bounds__(POTRF_THREADS) void k_potrf(TileView tv, int k) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked POTRF of the FP64 diagonal tile k, spread over several workgroups:
+// the tile is split into SB x SB blocks and, for each block column j,
+//   (a) k_potrf_block  one workgroup factors the diagonal block D_jj
+//                      (left-looking over 32-column panels inside the block),
+//   (b) k_potrf_panel  the rows below solve X D_jj^T = A (64 rows each),
+//   (c) k_potrf_syrk   the lower trailing part loses L_{:,j} L_{:,j}^T
+//                      (64 x 64 output blocks, FP64 MFMA).
+// A single-workgroup factorisation is bounded by one CU's FP64 MFMA rate
+// (nb^3/3 flops); here only (a), about SB^2 nb / 3 flops, runs on one CU.
+// ---------------------------------------------------------------------------
+constexpr int SB = 128;
+
+// 64-bit lane broadcast: the value v of lane src, read as a wave-uniform scalar.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, src);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Unblocked Cholesky of a 32 x 32 block held one row per lane (lane r < 32:
+// x[c] = D[r][c], c <= r), by one wave with lane broadcasts and no barriers.
+// Returns the first column whose pivot is not positive, or -1.
+__device__ __forceinline__ int chol32_wave(double (&x)[PW], int lane) {
+#pragma unroll
+  for (int c = 0; c < PW; ++c) {
+    const double d = readlane_f64(x[c], c);
+    if (!(d > 0.0)) return c;
+    const double piv = sqrt(d);
+    const double lc = (lane == c) ? piv : x[c] / piv;
+    x[c] = lc;
+#pragma unroll
+    for (int q = c + 1; q < PW; ++q) {
+      const double lq = readlane_f64(lc, q);
+      if (lane >= q) x[q] -= lc * lq;
+    }
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j) {
+  if (*tv.info) return;
+  const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
+  double* A = (double*)tv.tile(k, k);
+  __shared__ double D[PW][PW + 1];
+  __shared__ int fail;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) fail = 0;
+  for (int J0 = c0; J0 < c1; J0 += PW) {
+    // (1) A[J0:c1, J] -= L[J0:c1, c0:J0] L[J, c0:J0]^T, 16-row blocks over the 4 waves
+    if (J0 > c0) {
+      for (int rb = wave; rb < (c1 - J0) / 16; rb += 4) {
+        const int R0 = J0 + rb * 16;
+        d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        mfma_rows16x32(A, A, nb, R0, J0, c0, J0, lane, acc0, acc1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int R = R0 + (lane >> 4) + 4 * r, c = lane & 15;
+          if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc0[r];
+          if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= acc1[r];
+        }
+      }
+      __syncthreads();
+    }
+    // (2) the 32 x 32 diagonal block, one wave
+    if (wave == 0) {
+      double x[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c)
+        x[c] = (lane < PW && c <= lane) ? A[(int64_t)(J0 + c) * nb + J0 + lane] : 0.0;
+      const int bad = chol32_wave(x, lane);
+      if (bad >= 0) {
+        if (lane == 0) {
+          fail = 1;
+          if (*tv.info == 0) *tv.info = k * nb + J0 + bad + 1;
+        }
+      } else if (lane < PW) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+          const double v = c <= lane ? x[c] : 0.0;
+          D[lane][c] = v;
+          if (c <= lane) A[(int64_t)(J0 + c) * nb + J0 + lane] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (fail) return;
+    // (3) rows J0+32 .. c1 of the block (fewer than SB): x L_JJ^T = a, one row per thread
+    if (tid < c1 - J0 - PW) {
+      const int R = J0 + PW + tid;
+      double x[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) x[c] = A[(int64_t)(J0 + c) * nb + R];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        double v = x[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
+        x[c] = v / D[c][c];
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + R] = x[c];
+    }
+    __syncthreads();
+  }
+  // the strictly upper part of columns c0 .. c1 is zero in the factor
+  for (int e = tid; e < SB * c1; e += 256) {
+    const int r = e % c1, c = c0 + e / c1;
+    if (r < c) A[(int64_t)c * nb + r] = 0.0;
+  }
+}
+
+// rows c1 .. nb of block column j: X D_jj^T = A in place, 64 rows per workgroup
+__global__ __launch_bounds__(256) void k_potrf_panel(TileView tv, int k, int j) {
+  if (*tv.info) return;
+  const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
+  double* A = (double*)tv.tile(k, k);
+  const int r0 = c1 + blockIdx.x * 64;
+  __shared__ double T[64][PW + 1];
+  __shared__ double D[PW][PW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int J0 = c0; J0 < c1; J0 += PW) {
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    mfma_rows16x32(A, A, nb, r0 + wave * 16, J0, c0, J0, lane, acc0, acc1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lr = wave * 16 + (lane >> 4) + 4 * r, c = lane & 15;
+      T[lr][c] = A[(int64_t)(J0 + c) * nb + r0 + lr] - acc0[r];
+      T[lr][c + 16] = A[(int64_t)(J0 + c + 16) * nb + r0 + lr] - acc1[r];
+    }
+    for (int e = tid; e < PW * PW; e += 256) {
+      const int r = e % PW, c = e / PW;
+      D[r][c] = A[(int64_t)(J0 + c) * nb + J0 + r];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double x[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        double v = T[tid][c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
+        x[c] = v / D[c][c];
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + r0 + tid] = x[c];
+    }
+    __syncthreads();
+  }
+}
+
+// A[R, C] -= L[R, c0:c1] L[C, c0:c1]^T for c1 <= C <= R < nb; one workgroup per
+// lower 64 x 64 block (bi >= bj), wave w: rows 16w .. 16w+15 of the block
+__global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
+  if (*tv.info) return;
+  const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
+  double* A = (double*)tv.tile(k, k);
+  int bi = 0, rem = blockIdx.x;
+  while (rem > bi) { rem -= bi + 1; ++bi; }
+  const int bj = rem;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = c1 + bi * 64 + wave * 16, C0 = c1 + bj * 64;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    mfma_rows16x32(A, A, nb, R0, C0 + 32 * h, c0, c1, lane, acc0, acc1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 32 * h + (lane & 15);
+      if (R >= C) A[(int64_t)C * nb + R] -= acc0[r];
+      if (R >= C + 16) A[(int64_t)(C + 16) * nb + R] -= acc1[r];
+    }
+  }
+}
+
 hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
-  k_potrf<<<1, POTRF_THREADS, 0, s>>>(tv, k);
+  const int nsb = tv.nb / SB;
+  for (int j = 0; j < nsb; ++j) {
+    k_potrf_block<<<1, 256, 0, s>>>(tv, k, j);
+    const int rest = (tv.nb - (j + 1) * SB) / 64;  // 64-row blocks below block j
+    if (rest > 0) {
+      k_potrf_panel<<<rest, 256, 0, s>>>(tv, k, j);
+      k_potrf_syrk<<<rest * (rest + 1) / 2, 256, 0, s>>>(tv, k, j);
+    }
+  }
   return hipGetLastError();
 }
 
