@@ -171,7 +171,7 @@ struct mpcr_factor {
   uint8_t* d_fmt = nullptr;
   int* d_info = nullptr;
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles
-  double* d_Linv = nullptr;        // 2 nt nb^2 doubles (inverses and their transposes)
+  double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   bool linv_ready = false;
   GemmTask* d_tasks = nullptr;
@@ -413,7 +413,7 @@ int read_info(mpcr_ctx* ctx, mpcr_factor* f, int64_t* h_info) {
 
 int ensure_linv(mpcr_ctx* ctx, mpcr_factor* f) {
   if (f->linv_ready) return MPCR_OK;
-  if (!f->d_Linv) HIP_TRY(ctx, dmalloc(f->arena, &f->d_Linv, (size_t)2 * f->nt * f->nb * f->nb * 8));
+  if (!f->d_Linv) HIP_TRY(ctx, dmalloc(f->arena, &f->d_Linv, (size_t)f->nt * f->nb * f->nb * 8));
   const double nb3 = (double)f->nb * f->nb * f->nb;
   HIP_TRY(ctx, timed(ctx, ctx->stream, 7, nb3 / 3.0 * (double)f->nt,
                      [&] { return launch_trtri_diag(f->view(), f->d_Linv, ctx->stream); }));
@@ -685,7 +685,7 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
   size_t bytes = 0;
   bytes += (size_t)(nt * (nt + 1) / 2) * tile;            // tiles (FP64 bound)
   bytes += (size_t)std::max<int64_t>(nt - 1, 1) * tile;     // TRSM workspace
-  bytes += (size_t)2 * nt * tile;                           // inverted diagonal tiles
+  bytes += (size_t)nt * tile;                               // inverted diagonal tiles
   bytes += (size_t)solve_bytes(N, nrhs, n);                 // vectors
   bytes += (size_t)n * 24 + (size_t)nt * nt * 16 + 65536;   // sites, permutation, tables
   size_t npow2 = 1;

@@ -104,7 +104,10 @@ __device__ __forceinline__ void rmw_sub(void* Cp, int64_t idx, double acc) {
 template <int CF> struct KMajor {
   using T = typename CTraits<CF>::T;
   static constexpr int BK = (CF == F64) ? 16 : 32;
-  static constexpr int PAD = (CF == F64) ? 2 : 4;
+  // row padding: a fragment read covers 4 consecutive k rows of 16 elements;
+  // the padding puts those rows on disjoint LDS banks (row stride = 32 dwords
+  // mod 64 for FP64, 16 dwords mod 64 for FP32)
+  static constexpr int PAD = 16;
   static constexpr int G = BK / 8;  // 4-row groups per thread per operand
   using Acc = typename std::conditional<CF == F64, d4, f4>::type;
   using Buf = T[2][BK][UBM + PAD];
@@ -815,16 +818,15 @@ hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s) {
 // tile solves.  One workgroup per (tile, 32-column block J): block column J of
 // the inverse is the forward substitution L X = E_J, swept down the 32-row
 // blocks: X_IJ = D_I^{-1} (E_IJ - sum_{J <= M < I} L_IM X_MJ).
-// Linv (nt tiles, nb x nb column-major) and LinvT (their transposes) are written.
+// Linv holds nt tiles, nb x nb column-major.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trtri(TileView tv, double* Linv, double* LinvT) {
+__global__ __launch_bounds__(256) void k_trtri(TileView tv, double* Linv) {
   if (*tv.info) return;
   const int nb = tv.nb, nbl = nb / PW;
   const int kt = blockIdx.x / nbl;
   const int J = blockIdx.x % nbl, J0 = J * PW;
   const double* L = (const double*)tv.tile(kt, kt);
   double* X = Linv + (int64_t)kt * nb * nb;
-  double* XT = LinvT + (int64_t)kt * nb * nb;
   __shared__ double T[PW][PW + 1];
   __shared__ double D[PW][PW + 1];
   const int tid = threadIdx.x;
@@ -834,7 +836,6 @@ __global__ __launch_bounds__(256) void k_trtri(TileView tv, double* Linv, double
   for (int e = tid; e < J0 * PW; e += 256) {
     int r = e % J0, c = e / J0;
     X[(int64_t)(J0 + c) * nb + r] = 0.0;
-    XT[(int64_t)r * nb + J0 + c] = 0.0;
   }
   for (int I0 = J0; I0 < nb; I0 += PW) {
     double acc[4] = {0, 0, 0, 0};
@@ -863,18 +864,14 @@ __global__ __launch_bounds__(256) void k_trtri(TileView tv, double* Linv, double
         x[r] = v / D[r][r];
       }
 #pragma unroll
-      for (int r = 0; r < PW; ++r) {
-        X[(int64_t)(J0 + tid) * nb + I0 + r] = x[r];
-        XT[(int64_t)(I0 + r) * nb + J0 + tid] = x[r];
-      }
+      for (int r = 0; r < PW; ++r) X[(int64_t)(J0 + tid) * nb + I0 + r] = x[r];
     }
     __syncthreads();
   }
 }
 
 hipError_t launch_trtri_diag(const TileView& tv, double* Linv, hipStream_t s) {
-  const int64_t tile = (int64_t)tv.nb * tv.nb;
-  k_trtri<<<tv.nt * (tv.nb / PW), 256, 0, s>>>(tv, Linv, Linv + (int64_t)tv.nt * tile);
+  k_trtri<<<tv.nt * (tv.nb / PW), 256, 0, s>>>(tv, Linv);
   return hipGetLastError();
 }
 

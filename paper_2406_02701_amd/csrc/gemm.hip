@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
                                               void* Cv, int64_t ldc, int cprec) {
   using S = typename GTraits<P>::S;
   constexpr int BK = GTraits<P>::BK;
-  constexpr int PADK = 16 / (int)sizeof(S);
+  constexpr int PADK = 16;  // rows k, k+1 (FP64) or k .. k+3 (FP32) of a fragment on disjoint banks
   __shared__ __attribute__((aligned(16))) S As[BK][GB + PADK];
   __shared__ __attribute__((aligned(16))) S Bs[BK][GB + PADK];
 

@@ -13,9 +13,8 @@
 namespace mpcr {
 
 constexpr int RHS_CHUNK = 16;
-constexpr int GROWS = 64;    // output rows per workgroup of the panel products (64 rows x 4-way k split)
-constexpr int DROWS = 16;    // output rows per workgroup of the diagonal products (16 rows x 16-way k split):
-                             // only nb / DROWS workgroups run per step, so each does little
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int F>
 __device__ __forceinline__ double ldw(const void* p, int64_t i) {
@@ -26,212 +25,153 @@ __device__ __forceinline__ double ldw(const void* p, int64_t i) {
   else return (double)e4m3_to_f32(((const uint8_t*)p)[i]);
 }
 
-// out[r0 .. r0+63][c] (op) M[r0 .. r0+63][0 .. nb) V[0 .. nb)[c] for one nb x nb
-// column-major tile M.  Thread (r, h) handles row r over the k-quarter h with
-// sixteen right-hand sides in registers; V is staged in LDS (k-major, 16
-// values per k, read as broadcasts); the four quarters are added in a fixed
-// order.  mode 0: out = M V, mode 1: out -= M V.
-template <int F, int ROWS>
-__device__ void gemv_n_rows(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
-                            int nrhs, int mode, double* Vs /* nb x 16 */) {
-  constexpr int KS = 256 / ROWS;  // k-split of the 256 threads
-  const int tid = threadIdx.x, r = tid % ROWS, h = tid / ROWS;
-  const int kq = nb / KS, kb = h * kq;
-  double* part = Vs;  // 256 x 17 partial sums, written once the products are done
-  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
-    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
-    __syncthreads();
-    for (int e = tid; e < nb * RHS_CHUNK; e += 256) {
-      const int c = e / nb, k = e % nb;
-      Vs[k * RHS_CHUNK + c] = c < nc ? V[(int64_t)(c0 + c) * ldv + k] : 0.0;
+// The tile products of the solves and residuals are small GEMMs (nb x nb times
+// nb x 16 right-hand sides) done with FP64 MFMA 16x16x4.  They sit on the
+// sequential chain of the sweeps, so they are organised for latency: one
+// workgroup owns 16 output rows, its four waves split the contraction into
+// quarters and add their 16 x 16 partial products through LDS in a fixed
+// order.  Both operands are read straight from memory (the tile widened to
+// FP64 on load), eight k4 steps per batch with the next batch's loads issued
+// before the current batch's MFMAs.  Lane l supplies A[row = l % 16][k = l / 16]
+// and B[k = l / 16][c = l % 16]; the result lane l, register r is
+// D[l / 16 + 4 r][l % 16].
+constexpr int MB = 8;  // k4 steps per batch
+
+// acc0/acc1 += op(M)[row, k0 .. k1) * V[k0 .. k1, c], op(M)[row][k] = M[k * ldm + row]
+// (TRANS false) or M[row * ldm + k] (TRANS true); V is this lane's column of
+// the right-hand side (NULL: zero).  k1 - k0 is a multiple of 4 MB.
+template <int F, bool TRANS>
+__device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t row, int k0, int k1, const double* V,
+                                          int lane, d4& acc0, d4& acc1) {
+  const int q = lane >> 4;
+  double a[MB], b[MB], an[MB], bn[MB];
+  auto load = [&](int kk, double* da, double* db) {
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+      const int64_t k = kk + 4 * u + q;
+      da[u] = TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
+      db[u] = V ? V[k] : 0.0;
     }
-    __syncthreads();
-    double acc[RHS_CHUNK];
+  };
+  load(k0, a, b);
+  for (int kk = k0; kk < k1; kk += 4 * MB) {
+    const bool more = kk + 4 * MB < k1;
+    if (more) load(kk + 4 * MB, an, bn);
 #pragma unroll
-    for (int j = 0; j < RHS_CHUNK; ++j) acc[j] = 0.0;
-    const int64_t base = (int64_t)r0 + r;
-    // 32 independent loads per batch keep enough requests in flight to cover
-    // the memory latency at one wave per SIMD
-    constexpr int BATCH = 32;
-    for (int k0 = kb; k0 < kb + kq; k0 += BATCH) {
-      const int kn = (kb + kq - k0) < BATCH ? (kb + kq - k0) : BATCH;
-      double mv[BATCH];
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) mv[u] = u < kn ? ldw<F>(M, (int64_t)(k0 + u) * nb + base) : 0.0;
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) {
-        const double* vk = Vs + (k0 + u) * RHS_CHUNK;
-        if (u < kn) {
-#pragma unroll
-          for (int j = 0; j < RHS_CHUNK; ++j) acc[j] += mv[u] * vk[j];
-        }
-      }
+    for (int u = 0; u < MB; u += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 1], b[u + 1], acc1, 0, 0, 0);
     }
-    __syncthreads();
+    if (more) {
 #pragma unroll
-    for (int j = 0; j < RHS_CHUNK; ++j) part[tid * (RHS_CHUNK + 1) + j] = acc[j];
-    __syncthreads();
-    for (int e = tid; e < ROWS * RHS_CHUNK; e += 256) {
-      const int rr = e % ROWS, j = e / ROWS;
-      if (j < nc) {
-        double sum = 0.0;
-        for (int q = 0; q < KS; ++q) sum += part[(q * ROWS + rr) * (RHS_CHUNK + 1) + j];
-        double* o = out + (int64_t)(c0 + j) * ldo + r0 + rr;
-        *o = mode == 0 ? sum : *o - sum;
+      for (int u = 0; u < MB; ++u) {
+        a[u] = an[u];
+        b[u] = bn[u];
       }
     }
   }
 }
 
-// out[r0 .. r0+63][c] (op) sum_k M[k][r] V[k][c]: the transposed product.  The
-// columns r0 .. r0+63 of M are one contiguous block; it is staged through LDS in
-// 64 x 64 pieces (each thread loads 16 consecutive elements of one column).
-template <int F>
-__device__ void gemv_t_rows(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
-                            int nrhs, int mode, double* lds) {
-  double* Vc = lds;            // 64 x 16: the piece of V
-  double* S = lds + 64 * 16;   // 64 x 65: the piece of M, S[r][k] = M[k0 + k][r0 + r]
-  const int tid = threadIdx.x;
-  const int rr = tid & 63, q = tid >> 6;         // compute: row rr, right-hand sides 4q .. 4q+3
-  const int lr = tid >> 2, lc = (tid & 3) * 16;  // load: column r0+lr of M, rows lc .. lc+15 of the piece
+// out[r0 .. r0+15][c] (op)= sum_k op(M)[r0 + .., k] V[k][c] over one nb x nb tile M
+// (format F, column-major); mode 0: out = product, mode 1: out -= product.
+template <int F, bool TRANS>
+__device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
+                          int nrhs, int mode, double (*red)[16][17]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int kw = nb / 4;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
-    double acc[4] = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < nb; k0 += 64) {
-      __syncthreads();
-      for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
-        const int c = e / 64, k = e % 64;
-        Vc[k * RHS_CHUNK + c] = c < nc ? V[(int64_t)(c0 + c) * ldv + k0 + k] : 0.0;
-      }
-      const int64_t src = (int64_t)(r0 + lr) * nb + k0 + lc;
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    mfma_span<F, TRANS>(M, nb, r0 + c, w * kw, (w + 1) * kw, c < nc ? V + (int64_t)(c0 + c) * ldv : nullptr, lane,
+                        acc0, acc1);
 #pragma unroll
-      for (int e = 0; e < 16; ++e) S[lr * 65 + lc + e] = ldw<F>(M, src + e);
-      __syncthreads();
-#pragma unroll 8
-      for (int k = 0; k < 64; ++k) {
-        const double m = S[rr * 65 + k];
-        const double* vk = Vc + k * RHS_CHUNK + 4 * q;
+    for (int r = 0; r < 4; ++r) red[w][q + 4 * r][c] = acc0[r] + acc1[r];
+    __syncthreads();
+    if (w == 0 && c < nc) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] += m * vk[j];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = 4 * q + j;
-      if (c < nc) {
+      for (int r = 0; r < 4; ++r) {
+        const int rr = q + 4 * r;
+        const double v = ((red[0][rr][c] + red[1][rr][c]) + red[2][rr][c]) + red[3][rr][c];
         double* o = out + (int64_t)(c0 + c) * ldo + r0 + rr;
-        *o = mode == 0 ? acc[j] : *o - acc[j];
+        *o = mode == 0 ? v : *o - v;
       }
     }
+    __syncthreads();
   }
 }
 
-template <bool TRANS, int ROWS>
-__device__ void tile_gemv(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
-                          int64_t ldo, int nrhs, int mode, double* lds) {
-#define MPCR_GEMV_CASE(FMT)                                                                   \
-  case FMT:                                                                                  \
-    if (TRANS) gemv_t_rows<FMT>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);               \
-    else gemv_n_rows<FMT, ROWS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, lds);               \
-    break;
+template <bool TRANS>
+__device__ void tile_mfma_any(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
+                              int64_t ldo, int nrhs, int mode, double (*red)[16][17]) {
   switch (f) {
-    MPCR_GEMV_CASE(F64)
-    MPCR_GEMV_CASE(F32)
-    MPCR_GEMV_CASE(F16)
-    MPCR_GEMV_CASE(BF16)
-    MPCR_GEMV_CASE(F8)
+    case F64: tile_mfma<F64, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
+    case F32: tile_mfma<F32, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
+    case F16: tile_mfma<F16, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
+    case BF16: tile_mfma<BF16, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
+    default: tile_mfma<F8, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
   }
-#undef MPCR_GEMV_CASE
 }
 
-// dynamic LDS: the N product stages V for a whole tile (nb x 16 doubles, 128 KiB
-// at nb = 1024) and reuses it for the partial sums; the T product needs 64 x 16
-// + 64 x 65 doubles.
-static size_t gemv_lds(int nb) {
-  size_t n = (size_t)nb * RHS_CHUNK, t = 64 * RHS_CHUNK + 64 * 65, p = 256 * (RHS_CHUNK + 1);
-  size_t m = n > t ? n : t;
-  return (m > p ? m : p) * sizeof(double);
-}
-
+// one workgroup per 16 output rows
 __global__ __launch_bounds__(256) void k_fwd_diag(int nb, const double* Linv, int k, const double* R, double* W,
                                                   int64_t ld, int nrhs, const int* info) {
   if (*info) return;
-  extern __shared__ double lds[];
-  const int r0 = blockIdx.x * DROWS;
+  __shared__ double red[4][16][17];
   const int64_t off = (int64_t)k * nb;
-  tile_gemv<false, DROWS>(Linv + (int64_t)k * nb * nb, F64, nb, r0, R + off, ld, W + off, ld, nrhs, 0, lds);
+  tile_mfma<F64, false>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, R + off, ld, W + off, ld, nrhs, 0, red);
 }
 
 __global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
                                                     int nrhs) {
   if (*tv.info) return;
-  extern __shared__ double lds[];
-  const int nb = tv.nb, rb = nb / GROWS;
+  __shared__ double red[4][16][17];
+  const int nb = tv.nb, rb = nb / 16;
   const int i = k + 1 + blockIdx.x / rb;
-  const int r0 = (blockIdx.x % rb) * GROWS;
-  tile_gemv<false, GROWS>(tv.tile(i, k), tv.tfmt(i, k), nb, r0, W + (int64_t)k * nb, ld, R + (int64_t)i * nb, ld, nrhs, 1,
-                   lds);
+  tile_mfma_any<false>(tv.tile(i, k), tv.tfmt(i, k), nb, (blockIdx.x % rb) * 16, W + (int64_t)k * nb, ld,
+                       R + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
-__global__ __launch_bounds__(256) void k_bwd_diag(int nb, int nt, const double* Linv, int k, const double* V,
-                                                  double* X, int64_t ld, int nrhs, const int* info) {
+// X_k = Linv_kk^T V_k: the transposed product of the same inverse
+__global__ __launch_bounds__(256) void k_bwd_diag(int nb, const double* Linv, int k, const double* V, double* X,
+                                                  int64_t ld, int nrhs, const int* info) {
   if (*info) return;
-  extern __shared__ double lds[];
-  const int r0 = blockIdx.x * DROWS;
+  __shared__ double red[4][16][17];
   const int64_t off = (int64_t)k * nb;
-  const double* LinvT = Linv + (int64_t)nt * nb * nb + (int64_t)k * nb * nb;
-  tile_gemv<false, DROWS>(LinvT, F64, nb, r0, V + off, ld, X + off, ld, nrhs, 0, lds);
+  tile_mfma<F64, true>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, V + off, ld, X + off, ld, nrhs, 0, red);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
                                                     int nrhs) {
   if (*tv.info) return;
-  extern __shared__ double lds[];
-  const int nb = tv.nb, rb = nb / GROWS;
+  __shared__ double red[4][16][17];
+  const int nb = tv.nb, rb = nb / 16;
   const int i = blockIdx.x / rb;  // i < k
-  const int r0 = (blockIdx.x % rb) * GROWS;
-  tile_gemv<true, GROWS>(tv.tile(k, i), tv.tfmt(k, i), nb, r0, X + (int64_t)k * nb, ld, V + (int64_t)i * nb, ld, nrhs, 1,
-                  lds);
-}
-
-
-static hipError_t allow_big_lds() {
-  static hipError_t once = [] {
-    const int bytes = 160 * 1024;
-    hipError_t e = hipFuncSetAttribute((const void*)k_fwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_fwd_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_bwd_diag, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_bwd_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    return e;
-  }();
-  return once;
+  tile_mfma_any<true>(tv.tile(k, i), tv.tfmt(k, i), nb, (blockIdx.x % rb) * 16, X + (int64_t)k * nb, ld,
+                      V + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
                            int nrhs, hipStream_t s) {
-  if (hipError_t e = allow_big_lds(); e != hipSuccess) return e;
-  k_fwd_diag<<<tv.nb / DROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
+  k_fwd_diag<<<tv.nb / 16, 256, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
                              hipStream_t s) {
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
-  k_fwd_update<<<nt * (tv.nb / GROWS), 256, gemv_lds(tv.nb), s>>>(tv, k, R, W, ld, nrhs);
+  k_fwd_update<<<nt * (tv.nb / 16), 256, 0, s>>>(tv, k, R, W, ld, nrhs);
   return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
                            int nrhs, hipStream_t s) {
-  k_bwd_diag<<<tv.nb / DROWS, 256, gemv_lds(tv.nb), s>>>(tv.nb, tv.nt, Linv, k, V, X, ld, nrhs, tv.info);
+  k_bwd_diag<<<tv.nb / 16, 256, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* X, int64_t ld, int nrhs,
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  k_bwd_update<<<k * (tv.nb / GROWS), 256, gemv_lds(tv.nb), s>>>(tv, k, V, X, ld, nrhs);
+  k_bwd_update<<<k * (tv.nb / 16), 256, 0, s>>>(tv, k, V, X, ld, nrhs);
   return hipGetLastError();
 }
 
@@ -359,61 +299,68 @@ hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* 
 
 // ---------------------------------------------------------------------------
 // FP64 residual from the stored lower tiles of Sigma: row block (i, r0 .. r0+63)
-// of Sigma X is sum_{j <= i} S_ij X_j + sum_{j > i} S_ji^T X_j.  Every
-// workgroup streams one block row of Sigma in 64 x 64 pieces through LDS (the
-// transposed pieces are loaded column-wise, so all loads are contiguous) and
-// sums in a fixed order.
+// of Sigma X is sum_{j <= i} S_ij X_j + sum_{j > i} S_ji^T X_j, summed in order
+// of j with the FP64 MFMA tile product (each wave: 16 rows x 16 right-hand
+// sides).  With rowsum, ||Sigma||_inf's row sums sum_c |Sigma_rc| are formed
+// from the same loads.
 // ---------------------------------------------------------------------------
+// One workgroup per 16 rows, waves splitting every tile's columns in quarters
+// (as in the solves); with rowsum, ||Sigma||_inf's row sums sum_c |Sigma_rc| are
+// formed from a second pass over the same entries (cached).
 __global__ __launch_bounds__(256) void k_residual_tiles(int n, int nb, int nt, const double* sig, const double* B,
                                                         const double* X, double* R, int64_t ld, int nrhs,
                                                         double* rowsum) {
-  __shared__ double S[64][65];
-  __shared__ double Xc[64][RHS_CHUNK];
-  const int tid = threadIdx.x;
-  const int rb = nb / 64;
-  const int i = blockIdx.x / rb, r0 = (blockIdx.x % rb) * 64;
-  const int rr = tid & 63, q = tid >> 6;        // compute: row rr, right-hand sides 4q .. 4q+3
-  const int lr = tid >> 2, lc = (tid & 3) * 16;  // load: 16 consecutive elements of one column
+  __shared__ double red[4][16][17];
+  const int rb = nb / 16;
+  const int i = blockIdx.x / rb, r0 = (blockIdx.x % rb) * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int kw = nb / 4;
   const int64_t t2 = (int64_t)nb * nb;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
-    double acc[4] = {0, 0, 0, 0}, asum = 0.0;
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     for (int j = 0; j < nt; ++j) {
       const bool low = j <= i;
       const double* T = sig + tri_index(low ? i : j, low ? j : i) * t2;
-      for (int k0 = 0; k0 < nb; k0 += 64) {
-        __syncthreads();
-        for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
-          const int c = e / 64, k = e % 64;
-          Xc[k][c] = c < nc ? X[(int64_t)(c0 + c) * ld + (int64_t)j * nb + k0 + k] : 0.0;
-        }
-        if (low) {  // S[r][c] = T[k0 + c][r0 + r]: column k0+lr, rows r0+lc ..
-          const double* src = T + (int64_t)(k0 + lr) * nb + r0 + lc;
+      const double* Xj = c < nc ? X + (int64_t)(c0 + c) * ld + (int64_t)j * nb : nullptr;
+      if (low) mfma_span<F64, false>(T, nb, r0 + c, w * kw, (w + 1) * kw, Xj, lane, acc0, acc1);
+      else mfma_span<F64, true>(T, nb, r0 + c, w * kw, (w + 1) * kw, Xj, lane, acc0, acc1);
+    }
 #pragma unroll
-          for (int e = 0; e < 16; ++e) S[lc + e][lr] = src[e];
-        } else {    // S[r][c] = T[r0 + r][k0 + c]^T = T(col r0 + r, row k0 + c)
-          const double* src = T + (int64_t)(r0 + lr) * nb + k0 + lc;
+    for (int r = 0; r < 4; ++r) red[w][q + 4 * r][c] = acc0[r] + acc1[r];
+    __syncthreads();
+    if (w == 0 && c < nc) {
 #pragma unroll
-          for (int e = 0; e < 16; ++e) S[lr][lc + e] = src[e];
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int k = 0; k < 64; ++k) {
-          const double m = S[rr][k];
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) acc[jj] += m * Xc[k][4 * q + jj];
-          if (rowsum && c0 == 0 && q == 0) asum += fabs(m);
+      for (int r = 0; r < 4; ++r) {
+        const int rr = q + 4 * r;
+        const int grow = i * nb + r0 + rr;
+        if (grow < n) {
+          const double v = ((red[0][rr][c] + red[1][rr][c]) + red[2][rr][c]) + red[3][rr][c];
+          const int64_t o = (int64_t)(c0 + c) * ld + grow;
+          R[o] = (B ? B[o] : 0.0) - v;
         }
       }
     }
-    const int grow = i * nb + r0 + rr;
-    if (grow < n) {
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int c = 4 * q + jj;
-        if (c < nc) R[(int64_t)(c0 + c) * ld + grow] = (B ? B[(int64_t)(c0 + c) * ld + grow] : 0.0) - acc[jj];
-      }
-      if (rowsum && c0 == 0 && q == 0) rowsum[grow] = asum;
+    __syncthreads();
+  }
+  if (rowsum) {  // thread t: row t % 16, columns t / 16, t / 16 + 16, ...; partials added in order
+    const int rr = threadIdx.x & 15, cs = threadIdx.x >> 4;
+    double asum = 0.0;
+    for (int j = 0; j < nt; ++j) {
+      const bool low = j <= i;
+      const double* T = sig + tri_index(low ? i : j, low ? j : i) * t2;
+      for (int k = cs; k < nb; k += 16)
+        asum += fabs(low ? T[(int64_t)k * nb + r0 + rr] : T[(int64_t)(r0 + rr) * nb + k]);
+    }
+    double* part = &red[0][0][0];
+    part[threadIdx.x] = asum;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      double v = 0.0;
+      for (int h = 0; h < 16; ++h) v += part[h * 16 + rr];
+      const int grow = i * nb + r0 + rr;
+      if (grow < n) rowsum[grow] = v;
     }
   }
 }
@@ -421,7 +368,7 @@ __global__ __launch_bounds__(256) void k_residual_tiles(int n, int nb, int nt, c
 hipError_t launch_residual_tiles(int n, int nb, int nt, const double* sig64, const double* B, const double* X,
                                  double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum) {
   if (n == 0) return hipSuccess;
-  k_residual_tiles<<<nt * (nb / 64), 256, 0, s>>>(n, nb, nt, sig64, B, X, R, ld, nrhs, rowsum);
+  k_residual_tiles<<<nt * (nb / 16), 256, 0, s>>>(n, nb, nt, sig64, B, X, R, ld, nrhs, rowsum);
   return hipGetLastError();
 }
 
