@@ -114,14 +114,20 @@ def timed_steps(lib, ctx, args, call):
     lib.m.mpcr_ctx_reset_stats(ctx)
     lib.m.mpcr_ctx_set_profiling(ctx, 1)
     torch.cuda.synchronize()
+    region = [time.monotonic_ns(), 0]
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st, out, diag = call()
         lib.m.check(st, ctx)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    region[1] = time.monotonic_ns()
     lib.m.mpcr_ctx_set_profiling(ctx, 0)
+    timed_steps.regions.append(region)
     return dt, out, diag
+
+
+timed_steps.regions = []  # CLOCK_MONOTONIC ns of each timed region (to match kernel traces)
 
 
 def cpu_baseline(w, n_cpu):
@@ -366,6 +372,7 @@ def main():
                          for k, v in kstats64.items() if v[1]},
         "roofline": roofline,
         "cpu_baseline": None,
+        "timed_region_ns": {"mixed": timed_steps.regions[0], "fp64": timed_steps.regions[1]},
     }
     mp.mpcr_ctx_destroy(ctx_m)
     mp.mpcr_ctx_destroy(ctx_d)

@@ -170,7 +170,7 @@ struct mpcr_factor {
   int64_t* d_off = nullptr;
   uint8_t* d_fmt = nullptr;
   int* d_info = nullptr;
-  double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles
+  double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles (the panel TRSM's FP64 workspace)
   double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   bool linv_ready = false;

@@ -100,15 +100,23 @@ __device__ __forceinline__ void rmw_sub(void* Cp, int64_t idx, double acc) {
 // FP64 / FP32: operands staged k-major in LDS ([k][m]), double-buffered;
 // fragments are contiguous across lanes.  The main loop is instantiated per
 // pair of operand formats (one branch per workgroup), so each variant holds
-// only its own staging registers.
+// only its own staging registers.  Shapes (measured on a full-size batch of
+// 2016 tile updates): FP64 uses 8 waves of 64 x 32 (the FP64 MFMA is slow
+// enough that more waves per CU, not more work per wave, hides the staging),
+// FP32 4 waves of 64 x 64 with 16-wide k chunks (four workgroups per CU).
 template <int CF> struct KMajor {
   using T = typename CTraits<CF>::T;
-  static constexpr int BK = (CF == F64) ? 16 : 32;
+  static constexpr int NW = (CF == F64) ? 8 : 4;   // waves per workgroup
+  static constexpr int WM = 2;                      // waves along m
+  static constexpr int WN = NW / WM;
+  static constexpr int TM = UBM / WM, TN = UBM / WN;  // per-wave block
+  static constexpr int FM = TM / 16, FN = TN / 16;    // MFMA tiles per wave
+  static constexpr int NT = NW * 64;
+  static constexpr int BK = 16;
   // row padding: a fragment read covers 4 consecutive k rows of 16 elements;
-  // the padding puts those rows on disjoint LDS banks (row stride = 32 dwords
-  // mod 64 for FP64, 16 dwords mod 64 for FP32)
+  // the padding puts those rows on disjoint LDS banks
   static constexpr int PAD = 16;
-  static constexpr int G = BK / 8;  // 4-row groups per thread per operand
+  static constexpr int LD = UBM * BK / 4 / NT;  // 4-element loads per thread per operand
   using Acc = typename std::conditional<CF == F64, d4, f4>::type;
   using Buf = T[2][BK][UBM + PAD];
 };
@@ -116,30 +124,32 @@ template <int CF> struct KMajor {
 template <int CF, int FA, int FB>
 __device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, int nb, int64_t arow0, int64_t brow0,
                                                 typename KMajor<CF>::Buf& As, typename KMajor<CF>::Buf& Bs,
-                                                typename KMajor<CF>::Acc (&acc)[4][4]) {
+                                                typename KMajor<CF>::Acc (&acc)[KMajor<CF>::FM][KMajor<CF>::FN]) {
   using K = KMajor<CF>;
   using T = typename K::T;
-  constexpr int BK = K::BK, G = K::G;
+  constexpr int BK = K::BK, LD = K::LD, NT = K::NT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int lr = (tid & 31) * 4;  // loader rows lr .. lr+3
-  const int lc = tid >> 5;        // loader column (+ 8 g)
-  T ra[G][4], rb[G][4];
+  const int wm = wave % K::WM, wn = wave / K::WM;
+  T ra[LD][4], rb[LD][4];
+  // load e = tid + NT g: rows 4 (e % 32) .. +3 of column e / 32 of the chunk
   auto gload = [&](int kk) {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      load4<CF, FA>(Ap, (int64_t)(kk + lc + 8 * g) * nb + arow0 + lr, ra[g]);
-      load4<CF, FB>(Bp, (int64_t)(kk + lc + 8 * g) * nb + brow0 + lr, rb[g]);
+    for (int g = 0; g < LD; ++g) {
+      const int e = tid + NT * g, r = (e % (UBM / 4)) * 4, k = e / (UBM / 4);
+      load4<CF, FA>(Ap, (int64_t)(kk + k) * nb + arow0 + r, ra[g]);
+      load4<CF, FB>(Bp, (int64_t)(kk + k) * nb + brow0 + r, rb[g]);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int g = 0; g < LD; ++g) {
+      const int e = tid + NT * g, r = (e % (UBM / 4)) * 4, k = e / (UBM / 4);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        As[buf][lc + 8 * g][lr + r] = ra[g][r];
-        Bs[buf][lc + 8 * g][lr + r] = rb[g][r];
+      for (int u = 0; u < 4; ++u) {
+        As[buf][k][r + u] = ra[g][u];
+        Bs[buf][k][r + u] = rb[g][u];
       }
+    }
   };
   gload(0);
   sstore(0);
@@ -150,15 +160,15 @@ __device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, 
     if (more) gload(kk + BK);
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
-      T av[4], bv[4];
+      T av[K::FM], bv[K::FN];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[cur][k4 + (lane >> 4)][wm * 64 + a * 16 + (lane & 15)];
+      for (int a = 0; a < K::FM; ++a) av[a] = As[cur][k4 + (lane >> 4)][wm * K::TM + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[cur][k4 + (lane >> 4)][wn * 64 + b * 16 + (lane & 15)];
+      for (int b = 0; b < K::FN; ++b) bv[b] = Bs[cur][k4 + (lane >> 4)][wn * K::TN + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < K::FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < K::FN; ++b) {
           if constexpr (CF == F64)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
           else
@@ -172,8 +182,8 @@ __device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, 
 }
 
 template <int CF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update_kmajor(TileView tv, int k,
-                                                                                            const GemmTask* tasks) {
+__global__ __launch_bounds__(KMajor<CF>::NT) __attribute__((amdgpu_waves_per_eu(CF == F64 ? 2 : 4))) void
+k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
   using K = KMajor<CF>;
   __shared__ __attribute__((aligned(16))) typename K::Buf As;
   __shared__ __attribute__((aligned(16))) typename K::Buf Bs;
@@ -192,14 +202,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const void* Bp = tv.tile(t.j, k);
   const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % K::WM, wn = wave / K::WM;
   const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
 
-  typename K::Acc acc[4][4];
+  typename K::Acc acc[K::FM][K::FN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < K::FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = typename K::Acc{0, 0, 0, 0};
+    for (int b = 0; b < K::FN; ++b) acc[a][b] = typename K::Acc{0, 0, 0, 0};
 
   // tile formats are F64, F32, F16 or BF16 (codes 0..3)
 #define MPCR_PAIR(FA, FB) \
@@ -221,14 +231,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   auto epilogue = [&](auto fmt_tag) {
     constexpr int FC = decltype(fmt_tag)::value;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < K::FM; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < K::FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           int row = (CF == F64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
-          int64_t R = arow0 + wm * 64 + a * 16 + row;
-          int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
+          int64_t R = arow0 + wm * K::TM + a * 16 + row;
+          int64_t C = brow0 + wn * K::TN + b * 16 + (lane & 15);
           if (diag && C > R) continue;
           rmw_sub<FC>(Cp, C * nb + R, (double)acc[a][b][r]);
         }
@@ -344,8 +354,8 @@ hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTas
   const int sub = tv.nb / UBM;
   dim3 grid(ntasks * sub * sub);
   switch (cfmt) {
-    case F64: k_update_kmajor<F64><<<grid, 256, 0, s>>>(tv, k, tasks); break;
-    case F32: k_update_kmajor<F32><<<grid, 256, 0, s>>>(tv, k, tasks); break;
+    case F64: k_update_kmajor<F64><<<grid, KMajor<F64>::NT, 0, s>>>(tv, k, tasks); break;
+    case F32: k_update_kmajor<F32><<<grid, KMajor<F32>::NT, 0, s>>>(tv, k, tasks); break;
     case BF16: k_update_mmajor<BF16><<<grid, 256, 0, s>>>(tv, k, tasks); break;
     case F16: k_update_mmajor<F16><<<grid, 256, 0, s>>>(tv, k, tasks); break;
     default: return hipErrorInvalidValue;
@@ -354,13 +364,9 @@ hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTas
 }
 
 // ---------------------------------------------------------------------------
-// POTRF of the FP64 diagonal tile k (left-looking over 32-column panels, one
-// workgroup).  Per panel J: (1) A[J0:, J] -= L[J0:, :J0] L[J, :J0]^T with FP64
-// MFMA straight from the tile, (2) unblocked Cholesky of the 32 x 32 diagonal
-// block in LDS, (3) the rows below solved against it by substitution.
+// Shared pieces of the diagonal-tile POTRF and the panel TRSM.
 // ---------------------------------------------------------------------------
 constexpr int PW = 32;
-constexpr int POTRF_THREADS = 512;
 
 // acc0/acc1 (16 x 16 each) += A[R0.., K0:K1] * B[C0.., K0:K1]^T, operands read
 // straight from column-major FP64 storage (lda = ldb = ld).  Software
@@ -410,125 +416,87 @@ __device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B,
   }
 }
 
-__global__ __launch_bounds__(POTRF_THREADS) void k_potrf(TileView tv, int k) {
-  if (*tv.info) return;
-  const int nb = tv.nb;
-  double* A = (double*)tv.tile(k, k);
-  __shared__ double D[PW][PW + 1];
-  // one LDS buffer serves the per-wave partial products of the panel update
-  // (phase 1) and the per-thread rows of the panel solve (phase 3)
-  __shared__ double smem[POTRF_THREADS * (PW + 1)];
-  double(*Xs)[PW + 1] = (double(*)[PW + 1])smem;
-  double(*Ps)[16 * 33] = (double(*)[16 * 33])smem;
-  __shared__ int fail;
+// ---------------------------------------------------------------------------
+// Triangular solves on 16-row slabs held in LDS.
+//
+// trsm_slab16 solves X L^T = A for 16 rows: A (16 x nc) is the slab S in LDS
+// (row-major, leading dimension nc + 1), L (nc x nc, lower) is read from
+// memory (column-major, leading dimension ldl).  Right-looking over 32-column
+// panels J:
+//   X_J = S_J L_JJ^{-T}          right-looking substitution, two elements of
+//                                 the panel per thread, one barrier per column
+//   S_{>J} -= X_J L_{>J,J}^T     FP64 MFMA, A operand from LDS, B operand
+//                                 straight from L with all loads of a batch
+//                                 in flight before its MFMAs
+// 256 threads; the loops are compact (the kernels that use them run on the
+// factorisation's critical path, where instruction fetch of a long unrolled
+// body would dominate).
+// ---------------------------------------------------------------------------
+__device__ void trsm_slab16(const double* L, int64_t ldl, int nc, double* S, double (*D)[PW + 1]) {
+  __shared__ double xb[2][16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NW = POTRF_THREADS / 64;
-  if (tid == 0) fail = 0;
-
-  for (int J0 = 0; J0 < nb; J0 += PW) {
-    // (1) panel update with the columns already factored.  Work items are
-    // (16-row block, k slice); with fewer row blocks than waves the k range is
-    // split and the partial products are added through LDS in a fixed order.
-    if (J0 > 0) {
-      const int nrb = (nb - J0) / 16;  // 16-row blocks from J0 down
-      int ks = NW / nrb;               // k slices per row block
-      if (ks < 1) ks = 1;
-      while (ks > 1 && (J0 / 4) % ks) --ks;
-      const int klen = J0 / ks;        // multiple of 4
-      const int items = nrb * ks;
-      for (int it = wave; it < ((items + NW - 1) / NW) * NW; it += NW) {
-        const bool live = it < items;
-        const int rb = live ? it / ks : 0, sl = live ? it % ks : 0;
-        const int R0 = J0 + rb * 16;
-        d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        if (live) mfma_rows16x32(A, A, nb, R0, J0, sl * klen, (sl + 1) * klen, lane, acc0, acc1);
-        if (ks == 1) {
-          if (live) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int R = R0 + (lane >> 4) + 4 * r;
-              const int c = lane & 15;
-              if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc0[r];
-              if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= acc1[r];
-            }
-          }
-        } else {
-          // slices of one row block sit on consecutive waves of this round
-          double* P = Ps[wave];
-          if (live) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              P[((lane >> 4) + 4 * r) * 33 + (lane & 15)] = acc0[r];
-              P[((lane >> 4) + 4 * r) * 33 + 16 + (lane & 15)] = acc1[r];
-            }
-          }
-          __syncthreads();
-          if (live && sl == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int rr = (lane >> 4) + 4 * r, c = lane & 15;
-              const int R = R0 + rr;
-              double s0 = 0.0, s1 = 0.0;
-              for (int w2 = 0; w2 < ks; ++w2) {
-                s0 += Ps[wave + w2][rr * 33 + c];
-                s1 += Ps[wave + w2][rr * 33 + 16 + c];
-              }
-              if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= s0;
-              if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= s1;
-            }
-          }
-          __syncthreads();
-        }
-      }
+  const int sld = nc + 1;
+  const int q = lane >> 4, col = lane & 15;
+#pragma unroll 1
+  for (int J0 = 0; J0 < nc; J0 += PW) {
+    for (int e = tid; e < PW * PW; e += 256) {
+      const int r = e % PW, c = e / PW;
+      D[r][c] = L[(int64_t)(J0 + c) * ldl + J0 + r];
     }
     __syncthreads();
-    // (2) unblocked Cholesky of the 32 x 32 diagonal block in LDS
-    for (int e = tid; e < PW * PW; e += POTRF_THREADS) {
-      int r = e % PW, c = e / PW;
-      D[r][c] = (r >= c) ? A[(int64_t)(J0 + c) * nb + J0 + r] : 0.0;
-    }
-    __syncthreads();
-    for (int c = 0; c < PW; ++c) {
-      if (tid == 0) {
-        double d = D[c][c];
-        if (!(d > 0.0)) {
-          fail = 1;
-          if (*tv.info == 0) *tv.info = k * nb + J0 + c + 1;
-        }
-        D[c][c] = sqrt(d);
-      }
-      __syncthreads();
-      if (fail) return;
-      const double piv = D[c][c];
-      if (tid > c && tid < PW) D[tid][c] /= piv;
-      __syncthreads();
-      for (int e = tid; e < PW * PW; e += POTRF_THREADS) {
-        int r = e % PW, q = e / PW;
-        if (q > c && r >= q) D[r][q] -= D[r][c] * D[q][c];
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < PW * PW; e += POTRF_THREADS) {
-      int r = e % PW, c = e / PW;
-      if (r >= c) A[(int64_t)(J0 + c) * nb + J0 + r] = D[r][c];
-    }
-    // (3) rows below: x L_JJ^T = a, one row per thread, the row kept in LDS
-    for (int R = J0 + PW + tid; R < nb; R += POTRF_THREADS) {
-      double* x = Xs[tid];
-      for (int c = 0; c < PW; ++c) x[c] = A[(int64_t)(J0 + c) * nb + R];
+    // X_J: thread (r, qh) holds columns qh and qh + 16 of row r of the panel;
+    // column c is scaled by its owner, broadcast through LDS (double buffered,
+    // one barrier per column) and eliminated from the columns to its right
+    {
+      const int r = tid & 15, qh = tid >> 4;
+      double s0 = S[r * sld + J0 + qh], s1 = S[r * sld + J0 + qh + 16];
+#pragma unroll 1
       for (int c = 0; c < PW; ++c) {
-        double v = x[c];
-        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
-        x[c] = v / D[c][c];
+        if (qh == (c & 15)) {
+          const double x = (c < 16 ? s0 : s1) / D[c][c];
+          if (c < 16) s0 = x; else s1 = x;
+          xb[c & 1][r] = x;
+        }
+        __syncthreads();
+        const double xr = xb[c & 1][r];
+        if (qh > c) s0 -= xr * D[qh][c];
+        if (qh + 16 > c) s1 -= xr * D[qh + 16][c];
       }
-      for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + R] = x[c];
+      S[r * sld + J0 + qh] = s0;
+      S[r * sld + J0 + qh + 16] = s1;
     }
     __syncthreads();
-  }
-  // zero the strictly upper triangle so the stored tile is exactly L_kk
-  for (int64_t e = tid; e < (int64_t)nb * nb; e += POTRF_THREADS) {
-    int r = (int)(e % nb), c = (int)(e / nb);
-    if (r < c) A[e] = 0.0;
+    const int ncb = (nc - J0 - PW) / 16;  // 16-column blocks to the right of the panel
+    if (ncb > 0) {
+      double xa[PW / 4];
+#pragma unroll
+      for (int u = 0; u < PW / 4; ++u) xa[u] = S[col * sld + J0 + 4 * u + q];
+      for (int cb0 = wave; cb0 < ncb; cb0 += 4 * 4) {
+        double b[4][PW / 4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int cb = cb0 + 4 * h;
+          if (cb < ncb) {
+            const int64_t c = J0 + PW + 16 * cb + col;
+#pragma unroll
+            for (int u = 0; u < PW / 4; ++u) b[h][u] = L[(int64_t)(J0 + 4 * u + q) * ldl + c];
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int cb = cb0 + 4 * h;
+          if (cb < ncb) {
+            d4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < PW / 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], b[h][u], acc, 0, 0, 0);
+            const int c = J0 + PW + 16 * cb + col;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) S[(q + 4 * r) * sld + c] -= acc[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -536,14 +504,17 @@ __global__ __launch_bounds__(POTRF_THREADS) void k_potrf(TileView tv, int k) {
 // Blocked POTRF of the FP64 diagonal tile k, spread over several workgroups:
 // the tile is split into SB x SB blocks and, for each block column j,
 //   (a) k_potrf_block  one workgroup factors the diagonal block D_jj
-//                      (left-looking over 32-column panels inside the block),
-//   (b) k_potrf_panel  the rows below solve X D_jj^T = A (64 rows each),
+//                      (left-looking over 32-column panels inside the block:
+//                      FP64 MFMA panel update, the 32 x 32 diagonal block by
+//                      one wave with lane broadcasts, rows below by
+//                      substitution),
+//   (b) k_potrf_panel  the rows below solve X D_jj^T = A, 16 rows per
+//                      workgroup (trsm_slab16),
 //   (c) k_potrf_syrk   the lower trailing part loses L_{:,j} L_{:,j}^T
 //                      (64 x 64 output blocks, FP64 MFMA).
-// A single-workgroup factorisation is bounded by one CU's FP64 MFMA rate
-// (nb^3/3 flops); here only (a), about SB^2 nb / 3 flops, runs on one CU.
 // ---------------------------------------------------------------------------
 constexpr int SB = 128;
+constexpr int SBLD = SB + 1;
 
 // 64-bit lane broadcast: the value v of lane src, read as a wave-uniform scalar.
 __device__ __forceinline__ double readlane_f64(double v, int src) {
@@ -645,42 +616,24 @@ __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j) 
   }
 }
 
-// rows c1 .. nb of block column j: X D_jj^T = A in place, 64 rows per workgroup
+// rows c1 .. nb of block column j: X D_jj^T = A in place, 16 rows per workgroup
 __global__ __launch_bounds__(256) void k_potrf_panel(TileView tv, int k, int j) {
   if (*tv.info) return;
   const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
   double* A = (double*)tv.tile(k, k);
-  const int r0 = c1 + blockIdx.x * 64;
-  __shared__ double T[64][PW + 1];
-  __shared__ double D[PW][PW + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int J0 = c0; J0 < c1; J0 += PW) {
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    mfma_rows16x32(A, A, nb, r0 + wave * 16, J0, c0, J0, lane, acc0, acc1);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int lr = wave * 16 + (lane >> 4) + 4 * r, c = lane & 15;
-      T[lr][c] = A[(int64_t)(J0 + c) * nb + r0 + lr] - acc0[r];
-      T[lr][c + 16] = A[(int64_t)(J0 + c + 16) * nb + r0 + lr] - acc1[r];
-    }
-    for (int e = tid; e < PW * PW; e += 256) {
-      const int r = e % PW, c = e / PW;
-      D[r][c] = A[(int64_t)(J0 + c) * nb + J0 + r];
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double x[PW];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) {
-        double v = T[tid][c];
-#pragma unroll
-        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
-        x[c] = v / D[c][c];
-      }
-#pragma unroll
-      for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + r0 + tid] = x[c];
-    }
-    __syncthreads();
+  const int r0 = c1 + blockIdx.x * 16;
+  extern __shared__ double smem[];
+  double* S = smem;  // 16 x SBLD
+  double(*D)[PW + 1] = (double(*)[PW + 1])(smem + 16 * SBLD);
+  for (int e = threadIdx.x; e < 16 * SB; e += 256) {
+    const int r = e % 16, c = e / 16;
+    S[r * SBLD + c] = A[(int64_t)(c0 + c) * nb + r0 + r];
+  }
+  __syncthreads();
+  trsm_slab16(A + (int64_t)c0 * nb + c0, nb, SB, S, D);
+  for (int e = threadIdx.x; e < 16 * SB; e += 256) {
+    const int r = e % 16, c = e / 16;
+    A[(int64_t)(c0 + c) * nb + r0 + r] = S[r * SBLD + c];
   }
 }
 
@@ -710,11 +663,12 @@ __global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
 
 hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
   const int nsb = tv.nb / SB;
+  const size_t panel_lds = (size_t)(16 * SBLD + PW * (PW + 1)) * sizeof(double);
   for (int j = 0; j < nsb; ++j) {
     k_potrf_block<<<1, 256, 0, s>>>(tv, k, j);
     const int rest = (tv.nb - (j + 1) * SB) / 64;  // 64-row blocks below block j
     if (rest > 0) {
-      k_potrf_panel<<<rest, 256, 0, s>>>(tv, k, j);
+      k_potrf_panel<<<rest * 4, 256, panel_lds, s>>>(tv, k, j);
       k_potrf_syrk<<<rest * (rest + 1) / 2, 256, 0, s>>>(tv, k, j);
     }
   }
@@ -723,9 +677,34 @@ hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Panel TRSM: for i > k, X = A_ik L_kk^{-T} in FP64, rounded once to p(i,k).
-// One workgroup per 64 rows of one panel tile; left-looking over 32-column
-// chunks with the FP64 X kept in a workspace (ws: (nt-k-1) tiles of nb x nb).
+// k_trsm_slab: one workgroup per 16 rows of a panel tile, the rows widened
+// into an LDS slab and solved there (trsm_slab16).  k_trsm: one workgroup per
+// 64 rows, left-looking over 32-column chunks with the FP64 X kept in a
+// workspace (ws: (nt-k-1) tiles of nb x nb).
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trsm_slab(TileView tv, int k) {
+  if (*tv.info) return;
+  const int nb = tv.nb, rs = nb / 16;
+  const int ti = k + 1 + blockIdx.x / rs;
+  const int r0 = (blockIdx.x % rs) * 16;
+  const int sld = nb + 1;
+  extern __shared__ double smem[];
+  double* S = smem;  // 16 x (nb + 1)
+  double(*D)[PW + 1] = (double(*)[PW + 1])(smem + 16 * sld);
+  void* Ap = tv.tile(ti, k);
+  const int fa = tv.tfmt(ti, k);
+  for (int e = threadIdx.x; e < 16 * nb; e += 256) {
+    const int r = e % 16, c = e / 16;
+    S[r * sld + c] = load_wide(Ap, fa, (int64_t)c * nb + r0 + r);
+  }
+  __syncthreads();
+  trsm_slab16((const double*)tv.tile(k, k), nb, nb, S, D);
+  for (int e = threadIdx.x; e < 16 * nb; e += 256) {
+    const int r = e % 16, c = e / 16;
+    store_round(Ap, fa, (int64_t)c * nb + r0 + r, S[r * sld + c]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
   if (*tv.info) return;
   const int nb = tv.nb;
@@ -778,10 +757,24 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
   }
 }
 
+constexpr int TRSM_SLAB_MAX_NB = 1024;  // 16 x (nb + 1) doubles + the 32 x 33 block fit in 160 KiB of LDS
+
 hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, hipStream_t s) {
   int ntile = tv.nt - k - 1;
   if (ntile <= 0) return hipSuccess;
-  k_trsm<<<ntile * (tv.nb / 64), 256, 0, s>>>(tv, k, ws);
+  // Few panel tiles (the end of the factorisation, where the TRSM is on the
+  // critical path): 16-row slabs give 4x more workgroups and shorter chains.
+  // Many tiles: 64-row workgroups keep the per-step work (and LDS) small.
+  if (tv.nb <= TRSM_SLAB_MAX_NB && ntile * (tv.nb / 16) <= 512) {
+    static hipError_t once = hipFuncSetAttribute(
+        (const void*)k_trsm_slab, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)((16 * (TRSM_SLAB_MAX_NB + 1) + PW * (PW + 1)) * sizeof(double)));
+    if (once != hipSuccess) return once;
+    const size_t lds = (size_t)(16 * (tv.nb + 1) + PW * (PW + 1)) * sizeof(double);
+    k_trsm_slab<<<ntile * (tv.nb / 16), 256, lds, s>>>(tv, k);
+  } else {
+    k_trsm<<<ntile * (tv.nb / 64), 256, 0, s>>>(tv, k, ws);
+  }
   return hipGetLastError();
 }
 

@@ -337,7 +337,13 @@ def test_literal_bf16_band_map_breaks_down(g):
 
 def test_stored_and_matrix_free_residuals_agree(g):
     """Refinement with the FP64 residual streamed from a stored copy of Sigma's
-    tiles reaches the same log-likelihood as regenerating Sigma from the sites."""
+    tiles reaches the same log-likelihood as regenerating Sigma from the sites.
+    The two residuals round Sigma x differently (entry generation and summation
+    order), and the refined quadratic form z^T x + x^T r carries the residual's
+    rounding error |x^T dr| <~ n u ||Sigma|| ||x||^2; at this conditioning
+    (nugget 1e-5, nu = 5/2) that is ~1e-10 of the log-likelihood, so the two
+    agree to the 1e-9 used for refined log-likelihoods of ill-conditioned
+    matrices."""
     gu, ctx = g
     from paper_2406_02701_amd import mpcr
     n, nb = 1800, 128
@@ -352,7 +358,7 @@ def test_stored_and_matrix_free_residuals_agree(g):
         ctx.check(st)
         assert diag.converged == 1 and diag.eta <= 1e-13
         out.append((ll, diag))
-    np.testing.assert_allclose(out[0][0], out[1][0], rtol=1e-11)
+    np.testing.assert_allclose(out[0][0], out[1][0], rtol=1e-9)
     lo, zo, _ = loglik.order_sites(locs, z)
     ref = loglik.loglik_plain(lo, zo, 1.0, 0.05, 2.5, 1e-5)
     np.testing.assert_allclose(out[1][1].quad0, ref["quad"][0], rtol=1e-8)
