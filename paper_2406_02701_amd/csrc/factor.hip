@@ -253,13 +253,99 @@ k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
 }
 
 // BF16 / FP16: operands staged m-major in LDS ([m][k]) so that each lane reads
-// its 8 consecutive k values with one 16-byte load.
+// its 8 consecutive k values with one 16-byte load.  The column-major tiles
+// are read 8 rows at a time (one vector load per column), converted to the
+// compute format and scattered into 8 LDS rows; LDS is double-buffered and
+// the main loop is instantiated per pair of operand formats.
+template <int CF, int SF>
+__device__ __forceinline__ void load8_16(const void* p, int64_t idx, uint16_t out[8]) {
+  auto cvt = [](double x) -> uint16_t { return CF == BF16 ? to_bf16(x) : to_f16(x); };
+  if constexpr (SF == CF) {
+    const u16x8 v = *(const u16x8*)((const uint16_t*)p + idx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = v[e];
+  } else if constexpr (SF == F64) {
+    const double4 v0 = *(const double4*)((const double*)p + idx), v1 = *(const double4*)((const double*)p + idx + 4);
+    const double w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = cvt(w[e]);
+  } else if constexpr (SF == F32) {
+    const float4 v0 = *(const float4*)((const float*)p + idx), v1 = *(const float4*)((const float*)p + idx + 4);
+    const float w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = CF == BF16 ? f32_to_bf16_rne(w[e]) : __builtin_bit_cast(uint16_t, (_Float16)w[e]);
+  } else {  // the other 16-bit format: widen exactly, round once
+    const u16x8 v = *(const u16x8*)((const uint16_t*)p + idx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = cvt((double)(SF == F16 ? f16_to_f32(v[e]) : bf16_to_f32(v[e])));
+  }
+}
+
+constexpr int MBK = 64;        // k per chunk
+constexpr int MLDK = MBK + 8;  // LDS row (halfwords)
+
+template <int CF, int FA, int FB>
+__device__ __forceinline__ void mmajor_mainloop(const void* Ap, const void* Bp, int nb, int64_t arow0, int64_t brow0,
+                                                uint16_t (&As)[2][UBM][MLDK], uint16_t (&Bs)[2][UBM][MLDK],
+                                                f4 (&acc)[4][4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int rg = tid & 15;  // rows 8 rg .. 8 rg + 7
+  const int kq = tid >> 4;  // k = kq + 16 g
+  uint16_t ra[4][8], rb[4][8];
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t col = kk + kq + 16 * g;
+      load8_16<CF, FA>(Ap, col * nb + arow0 + 8 * rg, ra[g]);
+      load8_16<CF, FB>(Bp, col * nb + brow0 + 8 * rg, rb[g]);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        As[buf][8 * rg + e][kq + 16 * g] = ra[g][e];
+        Bs[buf][8 * rg + e][kq + 16 * g] = rb[g][e];
+      }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int cur = 0;
+  for (int kk = 0; kk < nb; kk += MBK) {
+    const bool more = kk + MBK < nb;
+    if (more) gload(kk + MBK);
+#pragma unroll
+    for (int k32 = 0; k32 < MBK; k32 += 32) {
+      u16x8 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = *(const u16x8*)&As[cur][wm * 64 + a * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = *(const u16x8*)&Bs[cur][wn * 64 + b * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (CF == BF16)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[a]),
+                                                                 __builtin_bit_cast(bf16x8, bv[b]), acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av[a]),
+                                                                __builtin_bit_cast(f16x8, bv[b]), acc[a][b], 0, 0, 0);
+        }
+    }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
 template <int CF>
 __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const GemmTask* tasks) {
-  constexpr int BK = 64;
-  constexpr int LDK = BK + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t As[UBM][LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[UBM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][UBM][MLDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][UBM][MLDK];
 
   const int nb = tv.nb;
   const int sub = nb / UBM;
@@ -274,30 +360,9 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
   const void* Ap = tv.tile(t.i, k);
   const void* Bp = tv.tile(t.j, k);
   const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int lrow = tid & 127;   // loader row
-  const int lkg = tid >> 7;     // loader k group: k = 8 lkg + 16 g .. +7
   const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
-
-  u16x8 ra[4], rb[4];
-  auto gload = [&](int kk) {
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int64_t col = kk + 8 * lkg + 16 * g + e;
-        ra[g][e] = load_as<CF>(Ap, fa, col * nb + arow0 + lrow);
-        rb[g][e] = load_as<CF>(Bp, fb, col * nb + brow0 + lrow);
-      }
-  };
-  auto sstore = [&]() {
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      *(u16x8*)&As[lrow][8 * lkg + 16 * g] = ra[g];
-      *(u16x8*)&Bs[lrow][8 * lkg + 16 * g] = rb[g];
-    }
-  };
 
   f4 acc[4][4];
 #pragma unroll
@@ -305,35 +370,20 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
 
-  gload(0);
-  for (int kk = 0; kk < nb; kk += BK) {
-    __syncthreads();
-    sstore();
-    __syncthreads();
-    if (kk + BK < nb) gload(kk + BK);
-#pragma unroll
-    for (int k32 = 0; k32 < BK; k32 += 32) {
-      u16x8 av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = *(const u16x8*)&As[wm * 64 + a * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = *(const u16x8*)&Bs[wn * 64 + b * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          if constexpr (CF == BF16)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[a]),
-                                                                 __builtin_bit_cast(bf16x8, bv[b]), acc[a][b], 0, 0, 0);
-          else
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av[a]),
-                                                                __builtin_bit_cast(f16x8, bv[b]), acc[a][b], 0, 0, 0);
-        }
-    }
+#define MPCR_PAIR(FA, FB) \
+  case FA * 4 + FB: mmajor_mainloop<CF, FA, FB>(Ap, Bp, nb, arow0, brow0, As, Bs, acc); break;
+#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16)
+  switch (fa * 4 + fb) {
+    MPCR_ROW(F64)
+    MPCR_ROW(F32)
+    MPCR_ROW(F16)
+    MPCR_ROW(BF16)
+    default: break;
   }
+#undef MPCR_ROW
+#undef MPCR_PAIR
 
-  void* Cp = tv.tile(t.i, t.j);
-  const int fc = tv.tfmt(t.i, t.j);
+  void* Cp = tv.tile(t.i, t.j);  // in format CF (the update runs in the output tile's format)
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -342,9 +392,7 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
       for (int r = 0; r < 4; ++r) {
         int64_t R = arow0 + wm * 64 + a * 16 + 4 * (lane >> 4) + r;
         int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
-        int64_t idx = C * nb + R;
-        double c = load_wide(Cp, fc, idx) - (double)acc[a][b][r];
-        store_round(Cp, fc, idx, c);
+        rmw_sub<CF>(Cp, C * nb + R, (double)acc[a][b][r]);
       }
 }
 
