@@ -559,6 +559,7 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
   }
   if ((rc = push_active()) != MPCR_OK) return rc;
   int it = 0;
+  bool r_true = true;  // R (and the fetched statistics) hold the true residual of the current X
   if (o.solver == 0 && nact > 0) {
     if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;  // z = M^{-1} r
     HIP_TRY(ctx, launch_copy_cols((int)b.N, nrhs, b.Z, ld, b.P, ld, s));
@@ -572,8 +573,10 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
       HIP_TRY(ctx, launch_axpy_cols(n, nrhs, alpha, -1.0, b.P, b.X, ld, s)); // x += alpha p
       if (o.recompute > 0 && it % o.recompute == 0) {
         HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+        r_true = true;
       } else {
         HIP_TRY(ctx, launch_axpy_cols(n, nrhs, alpha, -1.0, b.Q, b.R, ld, s)); // r -= alpha Sigma p
+        r_true = false;
       }
       if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
       bool any = false;
@@ -582,6 +585,7 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
         HIP_TRY(ctx, op.residual(b.B, b.X, b.W, ld, nrhs, s));
         if ((rc = fetch_stats(b.W)) != MPCR_OK) return rc;
         HIP_TRY(ctx, launch_copy_cols(n, nrhs, b.W, ld, b.R, ld, s));
+        r_true = true;
         for (int c = 0; c < nrhs; ++c)
           if (act[c] && col_converged(c)) {
             act[c] = 0;
@@ -613,9 +617,12 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
         }
     }
   }
-  // final true residual and statistics
-  HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
-  if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+  // final true residual and statistics (already current when the last step
+  // confirmed convergence with the true residual)
+  if (!r_true) {
+    HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+    if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+  }
   bool conv = true;
   double eta = 0, rel = 0;
   for (int c = 0; c < nrhs; ++c) {

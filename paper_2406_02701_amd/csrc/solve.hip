@@ -39,7 +39,8 @@ constexpr int MB = 8;  // k4 steps per batch
 
 // acc0/acc1 += op(M)[row, k0 .. k1) * V[k0 .. k1, c], op(M)[row][k] = M[k * ldm + row]
 // (TRANS false) or M[row * ldm + k] (TRANS true); V is this lane's column of
-// the right-hand side (NULL: zero).  k1 - k0 is a multiple of 4 MB.
+// the right-hand side (NULL: zero).  k1 - k0 is a multiple of 4; the k4 steps
+// of a batch past k1 read nothing and multiply zeros.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t row, int k0, int k1, const double* V,
                                           int lane, d4& acc0, d4& acc1) {
@@ -49,8 +50,9 @@ __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t ro
 #pragma unroll
     for (int u = 0; u < MB; ++u) {
       const int64_t k = kk + 4 * u + q;
-      da[u] = TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
-      db[u] = V ? V[k] : 0.0;
+      const bool in = kk + 4 * u < k1;
+      da[u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
+      db[u] = (V && in) ? V[k] : 0.0;
     }
   };
   load(k0, a, b);
