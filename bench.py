@@ -64,6 +64,9 @@ def parse():
                          "only if u_p max|Sigma_tile| <= guard * nugget")
     ap.add_argument("--residual", type=int, default=1,
                     help="refinement residual: 0 = regenerate Sigma from the sites, 1 = stream a stored FP64 copy")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy a buffer of this many MiB once before the timed steps (a plain copy of known size "
+                         "that scales hardware byte counters)")
     ap.add_argument("--tol", type=float, default=1e-13,
                     help="refinement stopping rule: normwise backward error per column (the metric's bar is 1e-9; "
                          "the default is tighter so that the log-likelihood matches the FP64 path)")
@@ -95,6 +98,22 @@ class Lib:
         ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self.m.check(self.m.mpcr_ctx_kernel_stats(ctx, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
         return ms.value, n.value, fl.value
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of `kind` from the committed counter summary (scaled
+    FETCH_SIZE + WRITE_SIZE), or None once the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tile_update_fp64_n32768_traffic.md")
+    if kind != "tile_update_fp64" or not os.path.exists(path):
+        return None
+    rec = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith(("|", "#")))
+    src = os.path.join(ROOT, "paper_2406_02701_amd", "csrc", "factor.hip")
+    if rec.get("kernel", "").strip() != kind or \
+            hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256", "").strip():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def banded(mp, n, nb, dmax, precs):
@@ -285,6 +304,13 @@ def main():
     opts = mp.mpcr_refine_opts_t(args.tol, 100, 0, 20, args.residual)
     flops = n ** 3 / 3 + 2 * n ** 2 * nrhs
 
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # maps: literal band map, its norm-guarded version, and all-FP64
     lit = banded(mp, n, nb, [2, 8, -1], [0, 1, 3])
     ctx_m = lib.ctx()
@@ -314,7 +340,9 @@ def main():
                                                                          None))
     kstats64 = {k: lib.stats(ctx_d, k) for k in range(NKIND)}
 
-    # dominant kernel of the mixed step (largest total time) and its roofline
+    # dominant kernel of the mixed step (largest total time) and its roofline;
+    # the tile updates, POTRF and TRSM are MFMA contractions (FP64 MFMA for the
+    # latter two); the other kinds are reported against FP64 as well
     dom = max(range(NKIND), key=lambda k: kstats[k][0])
     ms, launches, kfl = kstats[dom]
     avg_ms = ms / max(launches, 1)
@@ -323,8 +351,8 @@ def main():
     peak = PEAK_TFLOPS[dom] if dom <= 4 else PEAK_TFLOPS[0]
     bound = "mfma" if dom <= 7 else "alu"
     roofline = {"bound": bound, "kernel": KIND_NAME[dom], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "launches": launches, "avg_launch_ms": avg_ms,
-                "flops_per_launch": fl_per_launch}
+                "frac": achieved / peak, "traffic": measured_traffic(KIND_NAME[dom]), "traffic_unit": "bytes per launch",
+                "launches": launches, "avg_launch_ms": avg_ms, "flops_per_launch": fl_per_launch}
 
     fl_by = list(d_mix.flops_by_prec)
     tot = sum(fl_by)
