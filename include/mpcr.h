@@ -164,8 +164,10 @@ int mpcr_tilemap_banded(int64_t n, int64_t nb, const int* band_dmax, const int* 
 
 /* Norm-guarded map: starts from the banded map and promotes each off-diagonal
  * tile (i, j) to the lowest format p (in the order FP8 < FP16/BF16 < FP32 <
- * FP64, never below the banded choice's precision rule) whose unit roundoff
- * u_p satisfies u_p * max|Sigma_tile| <= guard.  h_tile_amax holds, row-major
+ * FP64, never below the banded choice's precision rule) whose rounding error
+ * bound satisfies max(u_p * max|Sigma_tile|, s_p / 2) <= guard, with u_p the
+ * unit roundoff and s_p the smallest subnormal of p (values below p's normal
+ * range round with absolute error up to s_p / 2: 2^-25 for FP16).  h_tile_amax holds, row-major
  * nt x nt, the largest magnitude of each lower tile (see
  * mpcr_covariance_tile_amax).  Writes nt*nt bytes to h_map_out. */
 int mpcr_tilemap_guarded(int64_t n, int64_t nb, const uint8_t* h_banded_map,

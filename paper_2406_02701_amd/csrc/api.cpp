@@ -818,12 +818,15 @@ int mpcr_tilemap_guarded(int64_t n, int64_t nb, const uint8_t* h_banded_map, con
       int p = h_banded_map[t];
       if (!valid_prec(p)) return MPCR_ERR_ARG;
       if (i == j && p != F64) return MPCR_ERR_ARG;
-      // promote until u_p * amax <= guard
-      while (p != F64 && fmt_unit_roundoff(p) * h_tile_amax[t] > guard) {
+      // promote until the rounding error bound max(u_p amax, floor_p) <= guard
+      auto too_coarse = [&](int f) {
+        return std::max(fmt_unit_roundoff(f) * h_tile_amax[t], fmt_abs_floor(f)) > guard;
+      };
+      while (p != F64 && too_coarse(p)) {
         int r = rank(p);
         p = r == 0 ? F16 : (r == 1 ? F32 : F64);
         if (rank(p) == 1 && h_banded_map[t] == BF16) p = BF16;  // stay in the map's 16-bit flavour
-        if (p == BF16 && fmt_unit_roundoff(BF16) * h_tile_amax[t] > guard) p = F32;
+        if (p == BF16 && too_coarse(BF16)) p = F32;
       }
       h_map_out[t] = (uint8_t)p;
     }

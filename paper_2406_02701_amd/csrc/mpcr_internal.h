@@ -27,6 +27,11 @@ __host__ __device__ inline int fmt_bytes(int f) {
 __host__ __device__ inline double fmt_unit_roundoff(int f) {
   return f == F64 ? 0x1p-53 : f == F32 ? 0x1p-24 : f == F16 ? 0x1p-11 : f == BF16 ? 0x1p-8 : 0x1p-4;
 }
+// Half the smallest subnormal: the absolute rounding error of values below the
+// normal range (FP8 is scaled per block or tile, so its floor is relative).
+__host__ __device__ inline double fmt_abs_floor(int f) {
+  return f == F64 ? 0x1p-1075 : f == F32 ? 0x1p-150 : f == F16 ? 0x1p-25 : f == BF16 ? 0x1p-134 : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // device rounding / widening

@@ -49,3 +49,21 @@ def theta(sigma2, range_, nu, nugget):
 
 def u8map(m: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(m.astype(np.uint8))
+
+
+def guarded_map(ctx, locs: np.ndarray, th, n: int, nb: int, start: np.ndarray, guard: float) -> np.ndarray:
+    """The norm-guarded version of `start` for the Morton-ordered covariance of
+    `locs` (per-tile max |Sigma| from the library, then mpcr_tilemap_guarded)."""
+    dl = dev(locs)
+    perm = torch.zeros(n, dtype=torch.int64, device="cuda")
+    ctx.check(mpcr.mpcr_morton_order(ctx.ptr, n, dl.data_ptr(), perm.data_ptr()))
+    dls = dev(locs[perm.cpu().numpy()])
+    nt = start.shape[0]
+    amax = np.zeros((nt, nt))
+    ctx.check(mpcr.mpcr_covariance_tile_amax(ctx.ptr, n, nb, dls.data_ptr(), ctypes.byref(th), mpcr.f64p(amax)))
+    out = np.zeros_like(start)
+    st0 = np.ascontiguousarray(start.astype(np.uint8))
+    mpcr.check(mpcr.mpcr_tilemap_guarded(n, nb, st0.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), mpcr.f64p(amax),
+                                         guard, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    torch.cuda.synchronize()
+    return out

@@ -83,6 +83,27 @@ def test_guarded_map_promotes_large_tiles():
     assert all(out[i, i] == 0 for i in range(nt))
 
 
+def test_guarded_map_fp16_subnormal_floor():
+    """FP16 rounds values below its normal range (6.1e-5) with absolute error
+    up to 2^-25 ~ 3.0e-8: with a guard below that, FP16 is never kept, however
+    small the tile; above it, the relative rule decides."""
+    nt = 3
+    banded = np.full((nt, nt), 255, np.uint8)
+    for i in range(nt):
+        for j in range(i + 1):
+            banded[i, j] = 0 if i == j else 2
+    amax = np.zeros((nt, nt))
+    amax[1, 0], amax[2, 0], amax[2, 1] = 1e-9, 1e-4, 1e-12
+    for guard, want in ((1e-8, 1), (1e-7, 2)):
+        out = np.zeros((nt, nt), np.uint8)
+        st = mpcr.mpcr_tilemap_guarded(nt * 128, 128, banded.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                       mpcr.f64p(amax), guard, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        assert st == 0
+        assert out[1, 0] == want and out[2, 1] == want
+        # 2^-11 * 1e-4 = 4.9e-8: FP16 only under the looser guard
+        assert out[2, 0] == (2 if 2.0 ** -11 * 1e-4 <= guard else 1)
+
+
 def test_null_context_arguments_are_rejected():
     assert mpcr.mpcr_ctx_create(0, None, None) == mpcr.MPCR_ERR_ARG
     assert mpcr.mpcr_ctx_destroy(None) == mpcr.MPCR_ERR_ARG
