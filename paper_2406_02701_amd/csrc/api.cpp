@@ -173,6 +173,7 @@ struct mpcr_factor {
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles (the panel TRSM's FP64 workspace)
   double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
+  double* d_rpart = nullptr;       // partial products of the stored residual
   bool linv_ready = false;
   GemmTask* d_tasks = nullptr;
   std::vector<int64_t> task_off;   // [(k * 5 + f)] offset into d_tasks
@@ -254,7 +255,7 @@ void free_factor(mpcr_factor* f) {
   if (!f) return;
   DeviceGuard g(f->device);
   for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
-                  (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig})
+                  (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig, (void*)f->d_rpart})
     dfree(f->arena, p);
   delete f;
 }
@@ -497,6 +498,7 @@ int tile_solve(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const double* Bsrc, 
 struct SigmaOp {
   mpcr_ctx* ctx = nullptr;  // for kernel timing
   const double* sig = nullptr;  // stored FP64 lower tiles (preferred when set)
+  double* part = nullptr;       // their partial-product workspace
   int nb = 0, nt = 0;
   const double* locs = nullptr;
   mpcr_theta_t th{};
@@ -506,7 +508,7 @@ struct SigmaOp {
   hipError_t residual(const double* B, const double* X, double* R, int64_t ld, int nrhs, hipStream_t s,
                       double* rowsum = nullptr) const {
     auto go = [&] {
-      if (sig) return launch_residual_tiles(n, nb, nt, sig, B, X, R, ld, nrhs, s, rowsum);
+      if (sig) return launch_residual_tiles(n, nb, nt, sig, B, X, R, ld, nrhs, s, rowsum, part);
       return A ? launch_residual_dense(n, A, lda, B, X, R, ld, nrhs, s, rowsum)
                : launch_residual_cov(n, locs, th, B, X, R, ld, nrhs, s, rowsum);
     };
@@ -1110,8 +1112,10 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   }
   HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), s));
   const bool stored_residual = opts && opts->max_iter > 0 && opts->residual == 1;
-  if (stored_residual && !f->d_sig)
+  if (stored_residual && !f->d_sig) {
     HIP_TRY(ctx, dmalloc(f->arena, &f->d_sig, (size_t)(f->nt * (f->nt + 1) / 2) * f->nb * f->nb * 8));
+    HIP_TRY(ctx, dmalloc(f->arena, &f->d_rpart, residual_part_bytes((int)f->nb, (int)f->nt)));
+  }
   HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s, stored_residual ? f->d_sig : nullptr));
   HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
   if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
@@ -1164,6 +1168,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     op.ctx = ctx;
     if (stored_residual) {
       op.sig = f->d_sig;
+      op.part = f->d_rpart;
       op.nb = (int)f->nb;
       op.nt = (int)f->nt;
     }

@@ -228,8 +228,9 @@ hipError_t launch_residual_dense(int n, const double* A, int64_t lda, const doub
                                  double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum = nullptr);
 // R = B - Sigma X from the FP64 copy of Sigma's lower tiles (B == NULL: R = -Sigma X);
 // rowsum != NULL also receives sum_c |Sigma_rc|
+size_t residual_part_bytes(int nb, int nt);
 hipError_t launch_residual_tiles(int n, int nb, int nt, const double* sig64, const double* B, const double* X,
-                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum = nullptr);
+                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum, double* part);
 hipError_t launch_rowsum_abs_cov(int n, const double* locs, const mpcr_theta_t& th, double* out,
                                  hipStream_t s);
 hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* out, hipStream_t s);

@@ -300,77 +300,186 @@ hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* 
 }
 
 // ---------------------------------------------------------------------------
-// FP64 residual from the stored lower tiles of Sigma: row block (i, r0 .. r0+63)
-// of Sigma X is sum_{j <= i} S_ij X_j + sum_{j > i} S_ji^T X_j, summed in order
-// of j with the FP64 MFMA tile product (each wave: 16 rows x 16 right-hand
-// sides).  With rowsum, ||Sigma||_inf's row sums sum_c |Sigma_rc| are formed
-// from the same loads.
+// FP64 residual from the stored lower tiles of Sigma, R = B - Sigma X.
+// Streaming pass: one workgroup per stored tile (i, j), j <= i, reads the tile
+// once (64 x 64 pieces staged through LDS, double-buffered, row of pieces by
+// row of pieces) and forms both of its products with FP64 MFMA:
+// P[i][j] = S_ij X_j (in registers along a row of pieces) and, off the
+// diagonal, P[j][i] = S_ij^T X_i (added into the partial block in order of the
+// piece rows; each element has one owner lane) - 16 right-hand sides per pass.  With rowsum it also
+// forms the |S| row and column sums.  A second kernel adds, for every row
+// block a, B_a - sum_b P[a][b] in the order b = 0, 1, ..., nt-1 (and the row
+// sums likewise), so results do not depend on scheduling.
+// Partials: nt x nt blocks of nb x 16 doubles, then nt x nt blocks of nb
+// doubles for the row sums.
 // ---------------------------------------------------------------------------
-// One workgroup per 16 rows, waves splitting every tile's columns in quarters
-// (as in the solves); with rowsum, ||Sigma||_inf's row sums sum_c |Sigma_rc| are
-// formed from a second pass over the same entries (cached).
-__global__ __launch_bounds__(256) void k_residual_tiles(int n, int nb, int nt, const double* sig, const double* B,
-                                                        const double* X, double* R, int64_t ld, int nrhs,
-                                                        double* rowsum) {
-  __shared__ double red[4][16][17];
-  const int rb = nb / 16;
-  const int i = blockIdx.x / rb, r0 = (blockIdx.x % rb) * 16;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int q = lane >> 4, c = lane & 15;
-  const int kw = nb / 4;
-  const int64_t t2 = (int64_t)nb * nb;
-  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
-    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    for (int j = 0; j < nt; ++j) {
-      const bool low = j <= i;
-      const double* T = sig + tri_index(low ? i : j, low ? j : i) * t2;
-      const double* Xj = c < nc ? X + (int64_t)(c0 + c) * ld + (int64_t)j * nb : nullptr;
-      if (low) mfma_span<F64, false>(T, nb, r0 + c, w * kw, (w + 1) * kw, Xj, lane, acc0, acc1);
-      else mfma_span<F64, true>(T, nb, r0 + c, w * kw, (w + 1) * kw, Xj, lane, acc0, acc1);
+constexpr int RP = 64;        // rows / columns of a staged piece
+constexpr int RPLD = RP + 2;  // LDS leading dimension (doubles) of a piece, [column][row]
+
+__global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const double* sig, const double* X, int64_t ld,
+                                                         int c0, int nc, double* part, int want_sum) {
+  __shared__ __attribute__((aligned(16))) double Sp[2][RP * RPLD];
+  __shared__ double red[4][RP];
+  int i = 0, rem = blockIdx.x;  // tile (i, j) from the packed lower index
+  while (rem > i) { rem -= i + 1; ++i; }
+  const int j = rem;
+  const bool diag = i == j;
+  const double* T = sig + (int64_t)blockIdx.x * nb * nb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
+  const int np = nb / RP;  // pieces per dimension (>= 2)
+  const int64_t blk = (int64_t)nb * RHS_CHUNK;
+  double* Pij = part + ((int64_t)i * nt + j) * blk;
+  double* Pji = part + ((int64_t)j * nt + i) * blk;
+  double* RSij = part + (int64_t)nt * nt * blk + ((int64_t)i * nt + j) * nb;
+  double* RSji = part + (int64_t)nt * nt * blk + ((int64_t)j * nt + i) * nb;
+  const bool cv = col < nc;
+  const double* Xj = X + (int64_t)(c0 + (cv ? col : 0)) * ld + (int64_t)j * nb;
+  const double* Xi = X + (int64_t)(c0 + (cv ? col : 0)) * ld + (int64_t)i * nb;
+
+  // Everything piece (pr, pc) needs from memory is requested one piece ahead:
+  // the piece itself (thread t: column t / 16 + 16 h, rows 4 (t % 16) .. +3),
+  // this lane's right-hand-side values for both products, and the running
+  // transposed partial it adds to.
+  double4 ld4[4];
+  double xn[RP / 4], xt[RP / 4], pold[4];
+  auto prefetch = [&](int pr, int pc) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = tid / 16 + 16 * h, r = 4 * (tid % 16);
+      ld4[h] = *(const double4*)(T + (int64_t)(RP * pc + c) * nb + RP * pr + r);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[w][q + 4 * r][c] = acc0[r] + acc1[r];
-    __syncthreads();
-    if (w == 0 && c < nc) {
+    for (int u = 0; u < RP / 4; ++u) {
+      xn[u] = cv ? Xj[RP * pc + 4 * u + q] : 0.0;
+      xt[u] = cv ? Xi[RP * pr + 4 * u + q] : 0.0;
+    }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = q + 4 * r;
-        const int grow = i * nb + r0 + rr;
-        if (grow < n) {
-          const double v = ((red[0][rr][c] + red[1][rr][c]) + red[2][rr][c]) + red[3][rr][c];
-          const int64_t o = (int64_t)(c0 + c) * ld + grow;
-          R[o] = (B ? B[o] : 0.0) - v;
+    for (int r = 0; r < 4; ++r)
+      pold[r] = (!diag && cv && pr > 0) ? Pji[(int64_t)col * nb + RP * pc + 16 * w + q + 4 * r] : 0.0;
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = tid / 16 + 16 * h, r = 4 * (tid % 16);
+      double* d = &Sp[buf][c * RPLD + r];
+      d[0] = ld4[h].x;
+      d[1] = ld4[h].y;
+      d[2] = ld4[h].z;
+      d[3] = ld4[h].w;
+    }
+  };
+  auto sum4 = [&](int r) { return ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]; };
+
+  prefetch(0, 0);
+  sstore(0);
+  double cxn[RP / 4], cxt[RP / 4], cpold[4];
+#pragma unroll
+  for (int u = 0; u < RP / 4; ++u) {
+    cxn[u] = xn[u];
+    cxt[u] = xt[u];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cpold[r] = pold[r];
+  __syncthreads();
+  int cur = 0;
+#pragma unroll 1
+  for (int pr = 0; pr < np; ++pr) {
+    d4 accN = {0, 0, 0, 0};  // rows 64 pr + 16 w .. of block i, summed over the column pieces
+    double rs = 0.0;         // |S| row sums of row 64 pr + tid % 64 (columns tid / 64 + 4 m of each piece)
+#pragma unroll 1
+    for (int pc = 0; pc < np; ++pc) {
+      const int nxt = pr * np + pc + 1;
+      const bool more = nxt < np * np;
+      if (more) prefetch(nxt / np, nxt % np);
+      const double* S = Sp[cur];
+#pragma unroll
+      for (int u = 0; u < RP / 4; ++u)  // N: row 64 pr + 16 w + col over the piece's columns
+        accN = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(4 * u + q) * RPLD + 16 * w + col], cxn[u], accN, 0, 0, 0);
+      if (!diag) {  // T: rows 64 pc + 16 w + col of block j over the piece's rows, added to P[j][i] in order of pr
+        d4 accT = {cpold[0], cpold[1], cpold[2], cpold[3]};
+#pragma unroll
+        for (int u = 0; u < RP / 4; ++u)
+          accT = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(16 * w + col) * RPLD + 4 * u + q], cxt[u], accT, 0, 0, 0);
+        if (cv) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Pji[(int64_t)col * nb + RP * pc + 16 * w + q + 4 * r] = accT[r];
         }
       }
+      if (want_sum) {
+        const int rr = tid % 64, g = tid / 64;
+        double cs = 0.0;
+        for (int m = g; m < RP; m += 4) {
+          rs += fabs(S[m * RPLD + rr]);
+          cs += fabs(S[rr * RPLD + m]);
+        }
+        if (!diag) {
+          red[g][rr] = cs;
+          __syncthreads();
+          if (tid < RP) RSji[RP * pc + tid] = pr == 0 ? sum4(tid) : RSji[RP * pc + tid] + sum4(tid);
+        }
+      }
+      if (more) {
+        sstore(cur ^ 1);
+#pragma unroll
+        for (int u = 0; u < RP / 4; ++u) {
+          cxn[u] = xn[u];
+          cxt[u] = xt[u];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cpold[r] = pold[r];
+      }
+      __syncthreads();
+      cur ^= 1;
     }
-    __syncthreads();
-  }
-  if (rowsum) {  // thread t: row t % 16, columns t / 16, t / 16 + 16, ...; partials added in order
-    const int rr = threadIdx.x & 15, cs = threadIdx.x >> 4;
-    double asum = 0.0;
-    for (int j = 0; j < nt; ++j) {
-      const bool low = j <= i;
-      const double* T = sig + tri_index(low ? i : j, low ? j : i) * t2;
-      for (int k = cs; k < nb; k += 16)
-        asum += fabs(low ? T[(int64_t)k * nb + r0 + rr] : T[(int64_t)(r0 + rr) * nb + k]);
+    if (cv) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Pij[(int64_t)col * nb + RP * pr + 16 * w + q + 4 * r] = accN[r];
     }
-    double* part = &red[0][0][0];
-    part[threadIdx.x] = asum;
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      double v = 0.0;
-      for (int h = 0; h < 16; ++h) v += part[h * 16 + rr];
-      const int grow = i * nb + r0 + rr;
-      if (grow < n) rowsum[grow] = v;
+    if (want_sum) {
+      red[tid / 64][tid % 64] = rs;
+      __syncthreads();
+      if (tid < RP) RSij[RP * pr + tid] = sum4(tid);
+      __syncthreads();
     }
   }
 }
 
+// R[row, c0 + c] = B - sum_b P[a][b][row, c] (b in order); rowsum[row] = sum_b RS[a][b][row]
+__global__ __launch_bounds__(256) void k_residual_reduce(int n, int nb, int nt, const double* part, const double* B,
+                                                         double* R, int64_t ld, int c0, int nc, double* rowsum) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int row = (int)(g % n), c = (int)(g / n);
+  if (c >= nc) return;
+  const int a = row / nb, r = row % nb;
+  const int64_t blk = (int64_t)nb * RHS_CHUNK;
+  double v = 0.0;
+  for (int b = 0; b < nt; ++b) v += part[((int64_t)a * nt + b) * blk + (int64_t)c * nb + r];
+  const int64_t o = (int64_t)(c0 + c) * ld + row;
+  R[o] = (B ? B[o] : 0.0) - v;
+  if (rowsum && c == 0) {
+    double t = 0.0;
+    for (int b = 0; b < nt; ++b) t += part[(int64_t)nt * nt * blk + ((int64_t)a * nt + b) * nb + r];
+    rowsum[row] = t;
+  }
+}
+
+size_t residual_part_bytes(int nb, int nt) {
+  return ((size_t)nt * nt * nb * RHS_CHUNK + (size_t)nt * nt * nb) * sizeof(double);
+}
+
 hipError_t launch_residual_tiles(int n, int nb, int nt, const double* sig64, const double* B, const double* X,
-                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum) {
+                                 double* R, int64_t ld, int nrhs, hipStream_t s, double* rowsum, double* part) {
   if (n == 0) return hipSuccess;
-  k_residual_tiles<<<nt * (nb / 16), 256, 0, s>>>(n, nb, nt, sig64, B, X, R, ld, nrhs, rowsum);
+  if (nb % RP != 0 || nb < 2 * RP || part == nullptr) return hipErrorInvalidValue;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
+    const int want = rowsum != nullptr && c0 == 0;
+    k_residual_stream<<<ntiles, 256, 0, s>>>(nb, nt, sig64, X, ld, c0, nc, part, want);
+    const int64_t total = (int64_t)n * nc;
+    k_residual_reduce<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(n, nb, nt, part, B, R, ld, c0, nc,
+                                                                        want ? rowsum : nullptr);
+  }
   return hipGetLastError();
 }
 
