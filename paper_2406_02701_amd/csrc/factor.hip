@@ -552,10 +552,11 @@ __device__ void trsm_slab16(const double* L, int64_t ldl, int nc, double* S, dou
 // Blocked POTRF of the FP64 diagonal tile k, spread over several workgroups:
 // the tile is split into SB x SB blocks and, for each block column j,
 //   (a) k_potrf_block  one workgroup factors the diagonal block D_jj
-//                      (left-looking over 32-column panels inside the block:
-//                      FP64 MFMA panel update, the 32 x 32 diagonal block by
+//                      (left-looking over 16-column panels inside the block:
+//                      FP64 MFMA panel update, the 16 x 16 diagonal block by
 //                      one wave with lane broadcasts, rows below by
-//                      substitution),
+//                      substitution; 16 columns keep the unrolled code small
+//                      enough to stay in the instruction cache),
 //   (b) k_potrf_panel  the rows below solve X D_jj^T = A, 16 rows per
 //                      workgroup (trsm_slab16),
 //   (c) k_potrf_syrk   the lower trailing part loses L_{:,j} L_{:,j}^T
@@ -572,19 +573,20 @@ __device__ __forceinline__ double readlane_f64(double v, int src) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Unblocked Cholesky of a 32 x 32 block held one row per lane (lane r < 32:
+// Unblocked Cholesky of an N x N block held one row per lane (lane r < N:
 // x[c] = D[r][c], c <= r), by one wave with lane broadcasts and no barriers.
 // Returns the first column whose pivot is not positive, or -1.
-__device__ __forceinline__ int chol32_wave(double (&x)[PW], int lane) {
+template <int N>
+__device__ __forceinline__ int chol_wave(double (&x)[N], int lane) {
 #pragma unroll
-  for (int c = 0; c < PW; ++c) {
+  for (int c = 0; c < N; ++c) {
     const double d = readlane_f64(x[c], c);
     if (!(d > 0.0)) return c;
     const double piv = sqrt(d);
     const double lc = (lane == c) ? piv : x[c] / piv;
     x[c] = lc;
 #pragma unroll
-    for (int q = c + 1; q < PW; ++q) {
+    for (int q = c + 1; q < N; ++q) {
       const double lq = readlane_f64(lc, q);
       if (lane >= q) x[q] -= lc * lq;
     }
@@ -592,45 +594,88 @@ __device__ __forceinline__ int chol32_wave(double (&x)[PW], int lane) {
   return -1;
 }
 
+// acc += A[R0 .. R0+15, K0:K1] * B[C0 .. C0+15, K0:K1]^T straight from
+// column-major FP64 storage (leading dimension ld), 16 k per batch with the
+// next batch's loads in flight.  K1 - K0 is a multiple of 4.
+__device__ __forceinline__ void mfma_rows16x16(const double* A, const double* B, int64_t ld, int R0, int C0, int K0,
+                                               int K1, int lane, d4& acc) {
+  const int r = lane & 15, q = lane >> 4;
+  int kk = K0;
+  const int full_end = K0 + ((K1 - K0) / 16) * 16;
+  if (kk < full_end) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[(int64_t)(kk + 4 * u + q) * ld + R0 + r];
+      b[u] = B[(int64_t)(kk + 4 * u + q) * ld + C0 + r];
+    }
+    for (; kk < full_end; kk += 16) {
+      double na[4], nb4[4];
+      const bool more = kk + 16 < full_end;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          na[u] = A[(int64_t)(kk + 16 + 4 * u + q) * ld + R0 + r];
+          nb4[u] = B[(int64_t)(kk + 16 + 4 * u + q) * ld + C0 + r];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = na[u];
+          b[u] = nb4[u];
+        }
+      }
+    }
+  }
+  for (; kk < K1; kk += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(int64_t)(kk + q) * ld + R0 + r], B[(int64_t)(kk + q) * ld + C0 + r],
+                                               acc, 0, 0, 0);
+}
+
+constexpr int PB = 16;  // panel width inside the diagonal block
+
 __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j) {
   if (*tv.info) return;
   const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
   double* A = (double*)tv.tile(k, k);
-  __shared__ double D[PW][PW + 1];
+  __shared__ double D[PB][PB + 1];
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) fail = 0;
-  for (int J0 = c0; J0 < c1; J0 += PW) {
+#pragma unroll 1
+  for (int J0 = c0; J0 < c1; J0 += PB) {
     // (1) A[J0:c1, J] -= L[J0:c1, c0:J0] L[J, c0:J0]^T, 16-row blocks over the 4 waves
     if (J0 > c0) {
       for (int rb = wave; rb < (c1 - J0) / 16; rb += 4) {
         const int R0 = J0 + rb * 16;
-        d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        mfma_rows16x32(A, A, nb, R0, J0, c0, J0, lane, acc0, acc1);
+        d4 acc = {0, 0, 0, 0};
+        mfma_rows16x16(A, A, nb, R0, J0, c0, J0, lane, acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int R = R0 + (lane >> 4) + 4 * r, c = lane & 15;
-          if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc0[r];
-          if (R >= J0 + 16 + c) A[(int64_t)(J0 + 16 + c) * nb + R] -= acc1[r];
+          if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc[r];
         }
       }
       __syncthreads();
     }
-    // (2) the 32 x 32 diagonal block, one wave
+    // (2) the 16 x 16 diagonal block, one wave
     if (wave == 0) {
-      double x[PW];
+      double x[PB];
 #pragma unroll
-      for (int c = 0; c < PW; ++c)
-        x[c] = (lane < PW && c <= lane) ? A[(int64_t)(J0 + c) * nb + J0 + lane] : 0.0;
-      const int bad = chol32_wave(x, lane);
+      for (int c = 0; c < PB; ++c)
+        x[c] = (lane < PB && c <= lane) ? A[(int64_t)(J0 + c) * nb + J0 + lane] : 0.0;
+      const int bad = chol_wave<PB>(x, lane);
       if (bad >= 0) {
         if (lane == 0) {
           fail = 1;
           if (*tv.info == 0) *tv.info = k * nb + J0 + bad + 1;
         }
-      } else if (lane < PW) {
+      } else if (lane < PB) {
 #pragma unroll
-        for (int c = 0; c < PW; ++c) {
+        for (int c = 0; c < PB; ++c) {
           const double v = c <= lane ? x[c] : 0.0;
           D[lane][c] = v;
           if (c <= lane) A[(int64_t)(J0 + c) * nb + J0 + lane] = v;
@@ -639,21 +684,21 @@ __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j) 
     }
     __syncthreads();
     if (fail) return;
-    // (3) rows J0+32 .. c1 of the block (fewer than SB): x L_JJ^T = a, one row per thread
-    if (tid < c1 - J0 - PW) {
-      const int R = J0 + PW + tid;
-      double x[PW];
+    // (3) rows J0+16 .. c1 of the block (fewer than SB): x L_JJ^T = a, one row per thread
+    if (tid < c1 - J0 - PB) {
+      const int R = J0 + PB + tid;
+      double x[PB];
 #pragma unroll
-      for (int c = 0; c < PW; ++c) x[c] = A[(int64_t)(J0 + c) * nb + R];
+      for (int c = 0; c < PB; ++c) x[c] = A[(int64_t)(J0 + c) * nb + R];
 #pragma unroll
-      for (int c = 0; c < PW; ++c) {
+      for (int c = 0; c < PB; ++c) {
         double v = x[c];
 #pragma unroll
         for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
         x[c] = v / D[c][c];
       }
 #pragma unroll
-      for (int c = 0; c < PW; ++c) A[(int64_t)(J0 + c) * nb + R] = x[c];
+      for (int c = 0; c < PB; ++c) A[(int64_t)(J0 + c) * nb + R] = x[c];
     }
     __syncthreads();
   }
