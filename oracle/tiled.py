@@ -17,6 +17,10 @@ panel below it, SYRK/GEMM on the trailing tiles) and these readings:
   update runs in the output tile's format (operands converted to it on load),
   the product is accumulated exactly (FP64 model) and the result is rounded
   once to p;
+* an FP8-E4M3 tile carries one power-of-two scale 2^s per tile, s from the
+  largest magnitude of the values being rounded (the rule of the FP8 block
+  scales of the GEMM); every rounding to FP8 above, of a tile or of an operand
+  converted on load, chooses the scale from the tile it rounds;
 * n that is not a multiple of nb is padded with an identity block, which
   leaves the log-determinant and the solution of the leading block unchanged.
 """
@@ -25,10 +29,25 @@ from __future__ import annotations
 import numpy as np
 
 from .dense import NotPositiveDefinite, cholesky_lower, forward_substitution
-from .fpformat import CODE, fmt_of, round_to
+from .fpformat import CODE, FP8_E4M3, fmt_of, pow2_scale_exponent, round_to
 
 FP64_CODE = CODE["fp64"]
+FP8_CODE = CODE["fp8_e4m3"]
 UNUSED = 255
+
+
+def tile_scale_exponent(X: np.ndarray) -> int:
+    """Exponent s of an FP8 tile's scale 2^s (the largest s with max|X| 2^s <= 448)."""
+    return int(pow2_scale_exponent(np.max(np.abs(X)) if X.size else 0.0))
+
+
+def round_tile(X: np.ndarray, code: int) -> np.ndarray:
+    """A whole tile rounded to format `code`; FP8 tiles are decode(RNE(X 2^s)) 2^-s
+    with their own scale exponent s."""
+    if int(code) != FP8_CODE:
+        return round_to(X, code)
+    s = tile_scale_exponent(X)
+    return np.ldexp(round_to(np.ldexp(X, s), FP8_E4M3), -s)
 
 
 def num_tiles(n: int, nb: int) -> int:
@@ -101,7 +120,7 @@ def tile_cholesky_emulated(Sigma: np.ndarray, nb: int, tmap: np.ndarray):
         if p(i, i) != FP64_CODE:
             raise ValueError("diagonal tiles must be FP64")
         for j in range(i):
-            A[T(i, j)] = round_to(A[T(i, j)], p(i, j))
+            A[T(i, j)] = round_tile(A[T(i, j)], p(i, j))
     for k in range(nt):
         try:
             Lkk = cholesky_lower(A[T(k, k)])
@@ -111,12 +130,12 @@ def tile_cholesky_emulated(Sigma: np.ndarray, nb: int, tmap: np.ndarray):
         for i in range(k + 1, nt):
             # X L_kk^T = A_ik  <=>  L_kk X^T = A_ik^T
             X = forward_substitution(Lkk, A[T(i, k)].T).T
-            A[T(i, k)] = round_to(X, p(i, k))
+            A[T(i, k)] = round_tile(X, p(i, k))
         for j in range(k + 1, nt):
             Ljk = A[T(j, k)]
             A[T(j, j)] = A[T(j, j)] - Ljk @ Ljk.T
             for i in range(j + 1, nt):
                 f = p(i, j)
-                upd = round_to(A[T(i, k)], f) @ round_to(Ljk, f).T
-                A[T(i, j)] = round_to(A[T(i, j)] - upd, f)
+                upd = round_tile(A[T(i, k)], f) @ round_tile(Ljk, f).T
+                A[T(i, j)] = round_tile(A[T(i, j)] - upd, f)
     return dict(L=np.tril(A), info=0, N=N)

@@ -44,7 +44,7 @@ def test_fp64_tiles_equal_dense(n, nb):
 def test_low_precision_tiles_hold_format_values_and_bound():
     n, nb, rho = 512, 64, 0.5
     A = kms(n, rho)
-    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (3, "fp32"), (5, "fp16"), (None, "bf16")))
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (3, "fp32"), (4, "fp16"), (5, "fp8_e4m3"), (None, "bf16")))
     out = tiled.tile_cholesky_emulated(A, nb, m)
     assert out["info"] == 0
     L = out["L"]
@@ -52,7 +52,7 @@ def test_low_precision_tiles_hold_format_values_and_bound():
     for i in range(nt):
         for j in range(i):
             t = L[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
-            assert np.array_equal(ff.round_to(t, int(m[i, j])), t)
+            assert np.array_equal(tiled.round_tile(t, int(m[i, j])), t)
     i = np.arange(n)
     ref = np.where(i[:, None] >= i[None, :], rho ** (i[:, None] - i[None, :]) * math.sqrt(1 - rho ** 2), 0.0)
     ref[:, 0] = rho ** i
@@ -185,3 +185,62 @@ def test_three_tile_step_by_hand():
     # the narrowing of L10 matters here: without it the result is different
     A21_wrong = R(t(W, 2, 1) - R(L20, "bf16") @ L10.T, "bf16")
     assert not np.array_equal(A21_wrong, A21)
+
+
+def test_fp8_tile_rounding_scale_and_grid():
+    """An FP8 tile is held as E4M3 codes times 2^-s with s the largest integer
+    such that max|X| 2^s <= 448 (found here by a plain search), every stored
+    value lies on the E4M3 grid after scaling, and values in E4M3's normal range
+    round with relative error <= 2^-4."""
+    g = np.random.default_rng(70)
+    for scale in (1e-30, 3e-7, 1.0, 5e3):
+        X = g.standard_normal((32, 32)) * scale
+        amax = np.max(np.abs(X))
+        s = -200
+        while amax * 2.0 ** (s + 1) <= 448:
+            s += 1
+        assert tiled.tile_scale_exponent(X) == s
+        R = tiled.round_tile(X, ff.CODE["fp8_e4m3"])
+        Y = np.ldexp(R, s)
+        assert np.all(np.abs(Y) <= 448)
+        assert np.array_equal(ff.round_to(Y, ff.FP8_E4M3), Y)
+        normal = np.abs(np.ldexp(X, s)) >= 2.0 ** -6
+        assert np.all(np.abs(R - X)[normal] <= 2.0 ** -4 * np.abs(X)[normal])
+    assert tiled.tile_scale_exponent(np.zeros((4, 4))) == 0
+
+
+def test_three_tile_step_by_hand_fp8():
+    """The hand computation of the 3 x 3 tile case with tile (2, 1) in FP8: the
+    FP8 roundings are done with the GEMM oracle's block quantiser (one block
+    per tile), an independent implementation of the per-tile scale."""
+    from oracle import gemm as og
+    g = np.random.default_rng(61)
+    M = g.standard_normal((24, 24))
+    A = M @ M.T + 24 * np.eye(24)
+    m = np.full((3, 3), 255, np.uint8)
+    m[0, 0] = m[1, 1] = m[2, 2] = 0
+    m[1, 0] = 1            # fp32
+    m[2, 0] = 0            # fp64
+    m[2, 1] = 4            # fp8
+    out = tiled.tile_cholesky_emulated(A, 8, m)["L"]
+
+    def R(x, f):
+        if f == "fp8":
+            Q, S = og.fp8_block_quantize(x, block=8)
+            return og.fp8_block_dequantize(Q, S, block=8)
+        return ff.round_to(x, f)
+    t = lambda X, i, j: X[8 * i:8 * i + 8, 8 * j:8 * j + 8]
+    W = A.copy()
+    for (i, j, f) in [(1, 0, "fp32"), (2, 0, "fp64"), (2, 1, "fp8")]:
+        W[8 * i:8 * i + 8, 8 * j:8 * j + 8] = R(t(W, i, j), f)
+    L00 = np.linalg.cholesky(t(W, 0, 0))
+    L10 = R(np.linalg.solve(L00, t(W, 1, 0).T).T, "fp32")
+    L20 = np.linalg.solve(L00, t(W, 2, 0).T).T
+    A11 = t(W, 1, 1) - L10 @ L10.T
+    A22 = t(W, 2, 2) - L20 @ L20.T
+    A21 = R(t(W, 2, 1) - R(L20, "fp8") @ R(L10, "fp8").T, "fp8")
+    L11 = np.linalg.cholesky(A11)
+    L21 = R(np.linalg.solve(L11, A21.T).T, "fp8")
+    L22 = np.linalg.cholesky(A22 - L21 @ L21.T)
+    for (i, j, ref) in [(0, 0, L00), (1, 0, L10), (2, 0, L20), (1, 1, L11), (2, 1, L21), (2, 2, L22)]:
+        np.testing.assert_allclose(t(out, i, j), ref, rtol=1e-13, atol=1e-14)
