@@ -175,6 +175,15 @@ struct mpcr_factor {
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   double* d_rpart = nullptr;       // partial products of the stored residual
   bool linv_ready = false;
+  // FP8 tiles: per-tile scale exponents, and for FP8 output updates the panel
+  // maxima (two step-parity buffers of nt) and the FP32 staging of the new tiles
+  int8_t* d_sc = nullptr;
+  bool has_f8 = false;
+  double* d_pamax = nullptr;
+  double* d_tamax = nullptr;       // nt x nt tile maxima for the FP8 scales at generation
+  float* d_ws8 = nullptr;
+  unsigned* d_amax8 = nullptr;
+  int f8_maxP = 0, f8_maxU = 0;    // FP8 output tasks per step on the two streams
   GemmTask* d_tasks = nullptr;
   std::vector<int64_t> task_off;   // [(k * 5 + f)] offset into d_tasks
   std::vector<int> task_cnt;
@@ -192,6 +201,7 @@ struct mpcr_factor {
     tv.nt = (int)nt;
     tv.n = (int)n;
     tv.info = d_info;
+    tv.sc = d_sc;
     return tv;
   }
 };
@@ -255,7 +265,8 @@ void free_factor(mpcr_factor* f) {
   if (!f) return;
   DeviceGuard g(f->device);
   for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
-                  (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig, (void*)f->d_rpart})
+                  (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig, (void*)f->d_rpart, (void*)f->d_sc,
+                  (void*)f->d_pamax, (void*)f->d_tamax, (void*)f->d_ws8, (void*)f->d_amax8})
     dfree(f->arena, p);
   delete f;
 }
@@ -278,7 +289,6 @@ int check_map(mpcr_ctx* ctx, int64_t n, const mpcr_tilemap_t* map, std::vector<u
       int p = out[i * nt + j];
       CHECK_ARG(ctx, valid_prec(p), "map(%lld,%lld) = %d is not a format", (long long)i, (long long)j, p);
       if (i == j) CHECK_ARG(ctx, p == F64, "diagonal tile %lld must be FP64", (long long)i);
-      if (!allow_fp8) CHECK_ARG(ctx, p != F8, "FP8 tiles are not supported by the tile factorisation");
     }
   return MPCR_OK;
 }
@@ -329,9 +339,26 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
       f->task_cnt_next[k * 5 + p] = nx;
     }
   }
+  for (int64_t k = 0; k < nt; ++k) {
+    const int all = f->task_cnt[k * 5 + F8], nx = f->task_cnt_next[k * 5 + F8];
+    f->f8_maxP = std::max(f->f8_maxP, nx);
+    f->f8_maxU = std::max(f->f8_maxU, all - nx);
+  }
+  for (uint8_t p : f->fmt_packed) f->has_f8 |= (p == F8);
   hipError_t e;
   Arena* A = f->arena;
-  if ((e = dmalloc(A, &f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(A, &f->d_off, ntiles * 8)) != hipSuccess ||
+  if (f->has_f8) {
+    const size_t nf8 = (size_t)(f->f8_maxP + f->f8_maxU);
+    if ((e = dmalloc(A, &f->d_pamax, (size_t)2 * nt * 8)) != hipSuccess ||
+        (e = dmalloc(A, &f->d_tamax, (size_t)nt * nt * 8)) != hipSuccess ||
+        (e = dmalloc(A, &f->d_ws8, std::max<size_t>(nf8, 1) * nb * nb * 4)) != hipSuccess ||
+        (e = dmalloc(A, &f->d_amax8, std::max<size_t>(nf8, 1) * 4)) != hipSuccess) {
+      free_factor(f);
+      return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+  }
+  if ((e = dmalloc(A, &f->d_sc, std::max<int64_t>(ntiles, 1))) != hipSuccess ||
+      (e = dmalloc(A, &f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(A, &f->d_off, ntiles * 8)) != hipSuccess ||
       (e = dmalloc(A, &f->d_fmt, ntiles)) != hipSuccess || (e = dmalloc(A, &f->d_info, sizeof(int))) != hipSuccess ||
       (e = dmalloc(A, &f->d_trsm_ws, (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 8)) != hipSuccess ||
       (e = dmalloc(A, &f->d_tasks, std::max<size_t>(tasks.size(), 1) * sizeof(GemmTask))) != hipSuccess) {
@@ -339,7 +366,8 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
     return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
   hipStream_t s = ctx->stream;
-  if ((e = hipMemcpyAsync(f->d_off, f->off_packed.data(), ntiles * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+  if ((e = hipMemsetAsync(f->d_sc, 0, std::max<int64_t>(ntiles, 1), s)) != hipSuccess ||
+      (e = hipMemcpyAsync(f->d_off, f->off_packed.data(), ntiles * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(f->d_fmt, f->fmt_packed.data(), ntiles, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (tasks.size() &&
        (e = hipMemcpyAsync(f->d_tasks, tasks.data(), tasks.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s)) !=
@@ -371,7 +399,8 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   // U starts after everything queued on P so far (the tile fill)
   HIP_TRY(ctx, hipEventRecord(ev(2 * nt), P));
   HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * nt), 0));
-  static const int order[4] = {F64, F32, BF16, F16};
+  static const int order[5] = {F64, F32, BF16, F16, F8};
+  const int64_t nb2 = f->nb * f->nb;
   auto launch_updates = [&](int64_t k, hipStream_t s, bool next_col) -> int {
     for (int p : order) {
       const int all = f->task_cnt[k * 5 + p], nx = f->task_cnt_next[k * 5 + p];
@@ -381,15 +410,27 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
       // GEMM tiles count 2 nb^3, the SYRK (diagonal) tiles nb^3
       const double ndiag = (p == F64) ? (next_col ? 1.0 : (double)(nt - k - 2)) : 0.0;
       const double fl = nb3 * (2.0 * cnt - ndiag);
-      HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s); }));
+      if (p == F8) {  // each stream stages in its own part of the FP8 workspace
+        const int base = next_col ? 0 : f->f8_maxP;
+        const double* pamax = f->d_pamax + (k & 1) * nt;
+        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] {
+          return launch_tile_update_fp8(tv, (int)k, t, cnt, pamax, f->d_ws8 + (int64_t)base * nb2, f->d_amax8 + base, s);
+        }));
+      } else {
+        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s); }));
+      }
     }
     return MPCR_OK;
   };
   int rc;
   for (int64_t k = 0; k < nt; ++k) {
+    bool fp8_panel = false;
+    for (int64_t i = k + 1; i < nt; ++i) fp8_panel |= (f->map[i * nt + k] == F8);
     HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, P); }));
     HIP_TRY(ctx, timed(ctx, P, 6, nb3 * (double)(nt - k - 1),
-                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, P); }));
+                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, fp8_panel, P); }));
+    if (f->task_cnt[k * 5 + F8] > 0)  // operand scales of the FP8 updates (buffer of this step's parity)
+      HIP_TRY(ctx, launch_panel_amax(tv, (int)k, f->d_pamax + (k & 1) * nt, P));
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
     if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
     if ((rc = launch_updates(k, P, true)) != MPCR_OK) return rc;
@@ -910,6 +951,10 @@ int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda, c
   if ((rc = make_factor(ctx, n, nb, m, &f)) != MPCR_OK) return rc;
   *out = f;
   HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), ctx->stream));
+  if (f->has_f8) {  // FP8 tile scales from the tile maxima of the input
+    HIP_TRY(ctx, launch_dense_tile_amax((int)n, (int)nb, d_A, lda, f->d_tamax, ctx->stream));
+    HIP_TRY(ctx, launch_fp8_scales(f->view(), f->d_tamax, ctx->stream));
+  }
   HIP_TRY(ctx, launch_tiles_from_dense(f->view(), d_A, lda, ctx->stream));
   if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
   return read_info(ctx, f, h_info);
@@ -931,6 +976,10 @@ int mpcr_potrf_tiled_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, 
   if ((rc = make_factor(ctx, n, nb, m, &f)) != MPCR_OK) return rc;
   *out = f;
   HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), ctx->stream));
+  if (f->has_f8) {
+    HIP_TRY(ctx, launch_covariance_tile_amax((int)n, (int)nb, d_locs, *theta, f->d_tamax, ctx->stream));
+    HIP_TRY(ctx, launch_fp8_scales(f->view(), f->d_tamax, ctx->stream));
+  }
   HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), d_locs, *theta, ctx->stream));
   if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
   return read_info(ctx, f, h_info);
@@ -1115,6 +1164,10 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   if (stored_residual && !f->d_sig) {
     HIP_TRY(ctx, dmalloc(f->arena, &f->d_sig, (size_t)(f->nt * (f->nt + 1) / 2) * f->nb * f->nb * 8));
     HIP_TRY(ctx, dmalloc(f->arena, &f->d_rpart, residual_part_bytes((int)f->nb, (int)f->nt)));
+  }
+  if (f->has_f8) {
+    HIP_TRY(ctx, launch_covariance_tile_amax((int)n, (int)f->nb, locs, *theta, f->d_tamax, s));
+    HIP_TRY(ctx, launch_fp8_scales(f->view(), f->d_tamax, s));
   }
   HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s, stored_residual ? f->d_sig : nullptr));
   HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));

@@ -122,7 +122,8 @@ template <int CF> struct KMajor {
 };
 
 template <int CF, int FA, int FB>
-__device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, int nb, int64_t arow0, int64_t brow0,
+__device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, double ma, double mb, int nb,
+                                                int64_t arow0, int64_t brow0,
                                                 typename KMajor<CF>::Buf& As, typename KMajor<CF>::Buf& Bs,
                                                 typename KMajor<CF>::Acc (&acc)[KMajor<CF>::FM][KMajor<CF>::FN]) {
   using K = KMajor<CF>;
@@ -138,6 +139,14 @@ __device__ __forceinline__ void kmajor_mainloop(const void* Ap, const void* Bp, 
       const int e = tid + NT * g, r = (e % (UBM / 4)) * 4, k = e / (UBM / 4);
       load4<CF, FA>(Ap, (int64_t)(kk + k) * nb + arow0 + r, ra[g]);
       load4<CF, FB>(Bp, (int64_t)(kk + k) * nb + brow0 + r, rb[g]);
+      if constexpr (FA == F8) {  // FP8 tiles hold codes of v 2^s: scale back (exact)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[g][u] = (T)((double)ra[g][u] * ma);
+      }
+      if constexpr (FB == F8) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rb[g][u] = (T)((double)rb[g][u] * mb);
+      }
     }
   };
   auto sstore = [&](int buf) {
@@ -211,15 +220,17 @@ k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
 #pragma unroll
     for (int b = 0; b < K::FN; ++b) acc[a][b] = typename K::Acc{0, 0, 0, 0};
 
-  // tile formats are F64, F32, F16 or BF16 (codes 0..3)
+  // operand tiles in any format (codes 0..4; FP8 operands carry their scale)
+  const double ma = tv.tmul(t.i, k), mb = tv.tmul(t.j, k);
 #define MPCR_PAIR(FA, FB) \
-  case FA * 4 + FB: kmajor_mainloop<CF, FA, FB>(Ap, Bp, nb, arow0, brow0, As, Bs, acc); break;
-#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16)
-  switch (fa * 4 + fb) {
+  case FA * 5 + FB: kmajor_mainloop<CF, FA, FB>(Ap, Bp, ma, mb, nb, arow0, brow0, As, Bs, acc); break;
+#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16) MPCR_PAIR(FA, F8)
+  switch (fa * 5 + fb) {
     MPCR_ROW(F64)
     MPCR_ROW(F32)
     MPCR_ROW(F16)
     MPCR_ROW(BF16)
+    MPCR_ROW(F8)
     default: break;
   }
 #undef MPCR_ROW
@@ -258,7 +269,7 @@ k_update_kmajor(TileView tv, int k, const GemmTask* tasks) {
 // compute format and scattered into 8 LDS rows; LDS is double-buffered and
 // the main loop is instantiated per pair of operand formats.
 template <int CF, int SF>
-__device__ __forceinline__ void load8_16(const void* p, int64_t idx, uint16_t out[8]) {
+__device__ __forceinline__ void load8_16(const void* p, int64_t idx, uint16_t out[8], double mul) {
   auto cvt = [](double x) -> uint16_t { return CF == BF16 ? to_bf16(x) : to_f16(x); };
   if constexpr (SF == CF) {
     const u16x8 v = *(const u16x8*)((const uint16_t*)p + idx);
@@ -274,6 +285,13 @@ __device__ __forceinline__ void load8_16(const void* p, int64_t idx, uint16_t ou
     const float w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e) out[e] = CF == BF16 ? f32_to_bf16_rne(w[e]) : __builtin_bit_cast(uint16_t, (_Float16)w[e]);
+  } else if constexpr (SF == F8) {  // codes of v 2^s: widen, scale back (mul = 2^-s), round once
+    const uint2 v = *(const uint2*)((const uint8_t*)p + idx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint8_t c = (uint8_t)(((e < 4 ? v.x : v.y) >> (8 * (e & 3))) & 0xffu);
+      out[e] = cvt((double)e4m3_to_f32(c) * mul);
+    }
   } else {  // the other 16-bit format: widen exactly, round once
     const u16x8 v = *(const u16x8*)((const uint16_t*)p + idx);
 #pragma unroll
@@ -285,7 +303,8 @@ constexpr int MBK = 64;        // k per chunk
 constexpr int MLDK = MBK + 8;  // LDS row (halfwords)
 
 template <int CF, int FA, int FB>
-__device__ __forceinline__ void mmajor_mainloop(const void* Ap, const void* Bp, int nb, int64_t arow0, int64_t brow0,
+__device__ __forceinline__ void mmajor_mainloop(const void* Ap, const void* Bp, double ma, double mb, int nb,
+                                                int64_t arow0, int64_t brow0,
                                                 uint16_t (&As)[2][UBM][MLDK], uint16_t (&Bs)[2][UBM][MLDK],
                                                 f4 (&acc)[4][4]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -297,8 +316,8 @@ __device__ __forceinline__ void mmajor_mainloop(const void* Ap, const void* Bp, 
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int64_t col = kk + kq + 16 * g;
-      load8_16<CF, FA>(Ap, col * nb + arow0 + 8 * rg, ra[g]);
-      load8_16<CF, FB>(Bp, col * nb + brow0 + 8 * rg, rb[g]);
+      load8_16<CF, FA>(Ap, col * nb + arow0 + 8 * rg, ra[g], ma);
+      load8_16<CF, FB>(Bp, col * nb + brow0 + 8 * rg, rb[g], mb);
     }
   };
   auto sstore = [&](int buf) {
@@ -370,14 +389,16 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
 
+  const double ma = tv.tmul(t.i, k), mb = tv.tmul(t.j, k);
 #define MPCR_PAIR(FA, FB) \
-  case FA * 4 + FB: mmajor_mainloop<CF, FA, FB>(Ap, Bp, nb, arow0, brow0, As, Bs, acc); break;
-#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16)
-  switch (fa * 4 + fb) {
+  case FA * 5 + FB: mmajor_mainloop<CF, FA, FB>(Ap, Bp, ma, mb, nb, arow0, brow0, As, Bs, acc); break;
+#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16) MPCR_PAIR(FA, F8)
+  switch (fa * 5 + fb) {
     MPCR_ROW(F64)
     MPCR_ROW(F32)
     MPCR_ROW(F16)
     MPCR_ROW(BF16)
+    MPCR_ROW(F8)
     default: break;
   }
 #undef MPCR_ROW
@@ -394,6 +415,225 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
         int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
         rmw_sub<CF>(Cp, C * nb + R, (double)acc[a][b][r]);
       }
+}
+
+// ---------------------------------------------------------------------------
+// Updates of FP8 output tiles (the update runs in the output tile's format):
+// both operands are converted to FP8 on load with the scale of their own tile
+// (a stored FP8 tile keeps its codes; any other operand tile (i, k) is
+// quantised with the scale that its largest magnitude pamax[i] gives), the
+// products accumulate in FP32 through v_mfma_f32_16x16x32_fp8_fp8, and the new
+// tile C - 2^-(sA+sB) acc is formed in FP64 and staged in FP32 by round-to-odd
+// with its largest magnitude; k_requant_f8 then rounds it once to FP8 with the
+// scale of that maximum (the two roundings equal one: FP32 keeps two more bits
+// than E4M3 needs).
+// ---------------------------------------------------------------------------
+constexpr int FBK = 128;           // k per chunk
+constexpr int FLDK = FBK + 16;     // LDS row (bytes)
+
+template <int SF>
+__device__ __forceinline__ void load8_f8(const void* p, int64_t idx, uint8_t out[8], double qs) {
+  if constexpr (SF == F8) {
+    const uint2 v = *(const uint2*)((const uint8_t*)p + idx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = (uint8_t)(((e < 4 ? v.x : v.y) >> (8 * (e & 3))) & 0xffu);
+  } else if constexpr (SF == F64) {
+    const double4 v0 = *(const double4*)((const double*)p + idx), v1 = *(const double4*)((const double*)p + idx + 4);
+    const double w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = to_e4m3(w[e] * qs);
+  } else if constexpr (SF == F32) {
+    const float4 v0 = *(const float4*)((const float*)p + idx), v1 = *(const float4*)((const float*)p + idx + 4);
+    const float w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = to_e4m3((double)w[e] * qs);
+  } else {
+    const u16x8 v = *(const u16x8*)((const uint16_t*)p + idx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = to_e4m3((double)(SF == F16 ? f16_to_f32(v[e]) : bf16_to_f32(v[e])) * qs);
+  }
+}
+
+template <int FA, int FB>
+__device__ __forceinline__ void f8_mainloop(const void* Ap, const void* Bp, double qa, double qb, int nb, int64_t arow0,
+                                            int64_t brow0, uint8_t (&As)[2][UBM][FLDK], uint8_t (&Bs)[2][UBM][FLDK],
+                                            f4 (&acc)[4][4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int rg = tid & 15;  // rows 8 rg .. 8 rg + 7
+  const int kq = tid >> 4;  // k = kq + 16 g, g = 0 .. 7
+  uint8_t ra[8][8], rb[8][8];
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int g = 0; g < FBK / 16; ++g) {
+      const int64_t col = kk + kq + 16 * g;
+      load8_f8<FA>(Ap, col * nb + arow0 + 8 * rg, ra[g], qa);
+      load8_f8<FB>(Bp, col * nb + brow0 + 8 * rg, rb[g], qb);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int g = 0; g < FBK / 16; ++g)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        As[buf][8 * rg + e][kq + 16 * g] = ra[g][e];
+        Bs[buf][8 * rg + e][kq + 16 * g] = rb[g][e];
+      }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int cur = 0;
+  for (int kk = 0; kk < nb; kk += FBK) {
+    const bool more = kk + FBK < nb;
+    if (more) gload(kk + FBK);
+#pragma unroll
+    for (int k32 = 0; k32 < FBK; k32 += 32) {
+      long av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = *(const long*)&As[cur][wm * 64 + a * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = *(const long*)&Bs[cur][wn * 64 + b * 16 + (lane & 15)][k32 + 8 * (lane >> 4)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+// scale exponent of operand tile (i, k) as an FP8 operand
+__device__ __forceinline__ int operand_f8_scale(const TileView& tv, int i, int k, const double* pamax) {
+  return tv.tfmt(i, k) == F8 ? tv.tscale(i, k) : fp8_scale_exp(pamax[i]);
+}
+
+__global__ __launch_bounds__(256) void k_update_f8(TileView tv, int k, const GemmTask* tasks, const double* pamax,
+                                                   float* ws32, unsigned* amax32) {
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][UBM][FLDK];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][UBM][FLDK];
+  __shared__ float red[256];
+  const int nb = tv.nb;
+  const int sub = nb / UBM;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int task = lb / (sub * sub);
+  const int blk = lb % (sub * sub);
+  const int bm = blk % sub, bn = blk / sub;
+  const GemmTask t = tasks[task];
+  if (*tv.info) return;
+
+  const void* Ap = tv.tile(t.i, k);
+  const void* Bp = tv.tile(t.j, k);
+  const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
+  const int sa = operand_f8_scale(tv, t.i, k, pamax), sb = operand_f8_scale(tv, t.j, k, pamax);
+  const double qa = ldexp(1.0, sa), qb = ldexp(1.0, sb);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+#define MPCR_PAIR(FA, FB) \
+  case FA * 5 + FB: f8_mainloop<FA, FB>(Ap, Bp, qa, qb, nb, arow0, brow0, As, Bs, acc); break;
+#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16) MPCR_PAIR(FA, F8)
+  switch (fa * 5 + fb) {
+    MPCR_ROW(F64)
+    MPCR_ROW(F32)
+    MPCR_ROW(F16)
+    MPCR_ROW(BF16)
+    MPCR_ROW(F8)
+    default: break;
+  }
+#undef MPCR_ROW
+#undef MPCR_PAIR
+
+  const uint8_t* Cp = (const uint8_t*)tv.tile(t.i, t.j);
+  const double mc = ldexp(1.0, -tv.tscale(t.i, t.j)), mp = ldexp(1.0, -(sa + sb));
+  float* W = ws32 + (int64_t)task * nb * nb;
+  float m = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = arow0 + wm * 64 + a * 16 + 4 * (lane >> 4) + r;
+        const int64_t C = brow0 + wn * 64 + b * 16 + (lane & 15);
+        const int64_t idx = C * nb + R;
+        const float v = round_odd_f32((double)e4m3_to_f32(Cp[idx]) * mc - (double)acc[a][b][r] * mp);
+        W[idx] = v;
+        m = fmaxf(m, fabsf(v));
+      }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(&amax32[task], __float_as_uint(red[0]));  // non-negative floats order as integers
+}
+
+// one workgroup per (FP8 task, 16-column slab): round the staged tile once to FP8
+__global__ __launch_bounds__(256) void k_requant_f8(TileView tv, const GemmTask* tasks, const float* ws32,
+                                                    const unsigned* amax32) {
+  if (*tv.info) return;
+  const int nb = tv.nb, slabs = nb / 16;
+  const int task = blockIdx.x / slabs, c0 = (blockIdx.x % slabs) * 16;
+  const GemmTask t = tasks[task];
+  const int s = fp8_scale_exp((double)__uint_as_float(amax32[task]));
+  uint8_t* Cp = (uint8_t*)tv.tile(t.i, t.j);
+  const float* W = ws32 + (int64_t)task * nb * nb;
+  for (int e = threadIdx.x; e < 16 * nb; e += 256) {
+    const int64_t idx = (int64_t)(c0 + e / nb) * nb + e % nb;
+    Cp[idx] = to_e4m3(ldexp((double)W[idx], s));
+  }
+  if (blockIdx.x % slabs == 0 && threadIdx.x == 0) tv.sc[tri_index(t.i, t.j)] = (int8_t)s;
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_tile_update_fp8(const TileView& tv, int k, const GemmTask* tasks, int ntasks, const double* pamax,
+                                  float* ws32, unsigned* amax32, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  const int sub = tv.nb / UBM;
+  k_zero_u32<<<(ntasks + 255) / 256, 256, 0, s>>>(amax32, ntasks);
+  k_update_f8<<<ntasks * sub * sub, 256, 0, s>>>(tv, k, tasks, pamax, ws32, amax32);
+  k_requant_f8<<<ntasks * (tv.nb / 16), 256, 0, s>>>(tv, tasks, ws32, amax32);
+  return hipGetLastError();
+}
+
+// largest magnitude of each panel tile (i, k), i > k (widened values)
+__global__ __launch_bounds__(256) void k_panel_amax(TileView tv, int k, double* pamax) {
+  const int i = k + 1 + blockIdx.x;
+  const int nb = tv.nb;
+  const void* P = tv.tile(i, k);
+  const int f = tv.tfmt(i, k);
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += 256) m = fmax(m, fabs(load_wide(P, f, e)));
+  red[threadIdx.x] = m * tv.tmul(i, k);
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pamax[i] = red[0];
+}
+
+hipError_t launch_panel_amax(const TileView& tv, int k, double* pamax, hipStream_t s) {
+  const int cnt = tv.nt - k - 1;
+  if (cnt <= 0) return hipSuccess;
+  k_panel_amax<<<cnt, 256, 0, s>>>(tv, k, pamax);
+  return hipGetLastError();
 }
 
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
@@ -786,9 +1026,10 @@ __global__ __launch_bounds__(256) void k_trsm_slab(TileView tv, int k) {
   double(*D)[PW + 1] = (double(*)[PW + 1])(smem + 16 * sld);
   void* Ap = tv.tile(ti, k);
   const int fa = tv.tfmt(ti, k);
+  const double ma = tv.tmul(ti, k);
   for (int e = threadIdx.x; e < 16 * nb; e += 256) {
     const int r = e % 16, c = e / 16;
-    S[r * sld + c] = load_wide(Ap, fa, (int64_t)c * nb + r0 + r);
+    S[r * sld + c] = load_wide(Ap, fa, (int64_t)c * nb + r0 + r) * ma;
   }
   __syncthreads();
   trsm_slab16((const double*)tv.tile(k, k), nb, nb, S, D);
@@ -808,6 +1049,7 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
   void* Ap = tv.tile(ti, k);
   const int fa = tv.tfmt(ti, k);
   double* X = ws + (int64_t)(ti - k - 1) * nb * nb;  // column-major nb x nb, rows r0..r0+63 owned here
+  const double ma = tv.tmul(ti, k);
   __shared__ double T[64][PW + 1];
   __shared__ double D[PW][PW + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -820,8 +1062,8 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
     for (int r = 0; r < 4; ++r) {
       const int lr = wave * 16 + (lane >> 4) + 4 * r;
       const int c = lane & 15;
-      T[lr][c] = load_wide(Ap, fa, (int64_t)(J0 + c) * nb + r0 + lr) - acc0[r];
-      T[lr][c + 16] = load_wide(Ap, fa, (int64_t)(J0 + c + 16) * nb + r0 + lr) - acc1[r];
+      T[lr][c] = load_wide(Ap, fa, (int64_t)(J0 + c) * nb + r0 + lr) * ma - acc0[r];
+      T[lr][c + 16] = load_wide(Ap, fa, (int64_t)(J0 + c + 16) * nb + r0 + lr) * ma - acc1[r];
     }
     for (int e = tid; e < PW * PW; e += 256) {
       int r = e % PW, c = e / PW;
@@ -842,7 +1084,9 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
     }
     __syncthreads();
   }
-  // single rounding into the tile's own format
+  // single rounding into the tile's own format (FP8 tiles: by k_quant_panel_f8,
+  // once the whole tile's largest magnitude is known)
+  if (fa == F8) return;
   for (int e = tid; e < 64 * nb; e += 256) {
     int r = e % 64, c = e / 64;
     int64_t idx = (int64_t)c * nb + r0 + r;
@@ -850,11 +1094,38 @@ __global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
   }
 }
 
+// FP8 panel tiles after k_trsm: scale from the solved tile's largest magnitude,
+// then one rounding of every value (one workgroup per panel tile)
+__global__ __launch_bounds__(256) void k_quant_panel_f8(TileView tv, int k, const double* ws) {
+  const int ti = k + 1 + blockIdx.x;
+  if (*tv.info || tv.tfmt(ti, k) != F8) return;
+  const int nb = tv.nb;
+  const double* X = ws + (int64_t)blockIdx.x * nb * nb;
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += 256) m = fmax(m, fabs(X[e]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const int sc = fp8_scale_exp(red[0]);
+  uint8_t* P = (uint8_t*)tv.tile(ti, k);
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += 256) P[e] = to_e4m3(ldexp(X[e], sc));
+  if (threadIdx.x == 0) tv.sc[tri_index(ti, k)] = (int8_t)sc;
+}
+
 constexpr int TRSM_SLAB_MAX_NB = 1024;  // 16 x (nb + 1) doubles + the 32 x 33 block fit in 160 KiB of LDS
 
-hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, hipStream_t s) {
+hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, bool fp8_panel, hipStream_t s) {
   int ntile = tv.nt - k - 1;
   if (ntile <= 0) return hipSuccess;
+  if (fp8_panel) {  // FP8 tiles are rounded after the whole tile is solved
+    k_trsm<<<ntile * (tv.nb / 64), 256, 0, s>>>(tv, k, ws);
+    k_quant_panel_f8<<<ntile, 256, 0, s>>>(tv, k, ws);
+    return hipGetLastError();
+  }
   // Few panel tiles (the end of the factorisation, where the TRSM is on the
   // critical path): 16-row slabs give 4x more workgroups and shorter chains.
   // Many tiles: 64-row workgroups keep the per-step work (and LDS) small.

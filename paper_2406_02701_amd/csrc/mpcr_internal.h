@@ -131,10 +131,27 @@ struct TileView {
   int nt;
   int n;                  // true (unpadded) order
   int* info;              // device: 0, or 1-based global column of a failed pivot
+  int8_t* sc;             // device: scale exponent s of each FP8 tile (values = codes * 2^-s)
 
   __device__ __forceinline__ void* tile(int i, int j) const { return base + off[tri_index(i, j)]; }
   __device__ __forceinline__ int tfmt(int i, int j) const { return fmt[tri_index(i, j)]; }
+  __device__ __forceinline__ int tscale(int i, int j) const { return sc[tri_index(i, j)]; }
+  // widening multiplier of tile (i, j): 2^-s for an FP8 tile, 1 otherwise
+  __device__ __forceinline__ double tmul(int i, int j) const {
+    return tfmt(i, j) == F8 ? ldexp(1.0, -tscale(i, j)) : 1.0;
+  }
 };
+
+// FP8 scale exponent of a tile or block with largest magnitude amax: the
+// largest s with amax * 2^s <= 448 (from the binary exponent, exact), 0 for an
+// all-zero block, clamped to a signed byte.
+__host__ __device__ inline int fp8_scale_exp(double amax) {
+  if (!(amax > 0.0)) return 0;
+  int E;
+  const double m = frexp(amax, &E);  // amax = m 2^E, m in [0.5, 1); 448 = 0.875 2^9
+  const int s = (m <= 0.875) ? 9 - E : 8 - E;
+  return s < -128 ? -128 : (s > 127 ? 127 : s);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs of an MI355X (workgroup
 // b runs on XCD b % 8), each with its own L2.  This remaps the launch index so
@@ -205,7 +222,16 @@ hipError_t launch_convert(int prec, int64_t m, int64_t n, const double* src, int
                           int64_t ldd, int8_t* scale_exp, hipStream_t s);
 
 hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s);
-hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, hipStream_t s);
+// FP8 tiles: per-tile scales from the tile maxima (amax: nt x nt, row-major)
+hipError_t launch_fp8_scales(const TileView& tv, const double* amax, hipStream_t s);
+hipError_t launch_dense_tile_amax(int n, int nb, const double* A, int64_t lda, double* amax, hipStream_t s);
+// largest magnitude of each panel tile (i, k), i > k -> pamax[i]
+hipError_t launch_panel_amax(const TileView& tv, int k, double* pamax, hipStream_t s);
+// updates with FP8 output tiles: FP8 MFMA (operands quantised per tile), the new
+// values staged in FP32 (ws32: cnt nb^2 floats, amax32: cnt words), then requantised
+hipError_t launch_tile_update_fp8(const TileView& tv, int k, const GemmTask* tasks, int ntasks, const double* pamax,
+                                  float* ws32, unsigned* amax32, hipStream_t s);
+hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, bool fp8_panel, hipStream_t s);
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
                               hipStream_t s);
 hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s);

@@ -43,7 +43,7 @@ constexpr int MB = 8;  // k4 steps per batch
 // of a batch past k1 read nothing and multiply zeros.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t row, int k0, int k1, const double* V,
-                                          int lane, d4& acc0, d4& acc1) {
+                                          int lane, d4& acc0, d4& acc1, double mul = 1.0) {
   const int q = lane >> 4;
   double a[MB], b[MB], an[MB], bn[MB];
   auto load = [&](int kk, double* da, double* db) {
@@ -52,6 +52,7 @@ __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t ro
       const int64_t k = kk + 4 * u + q;
       const bool in = kk + 4 * u < k1;
       da[u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
+      if constexpr (F == F8) da[u] *= mul;  // FP8 tiles hold codes of v 2^s
       db[u] = (V && in) ? V[k] : 0.0;
     }
   };
@@ -78,7 +79,7 @@ __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t ro
 // (format F, column-major); mode 0: out = product, mode 1: out -= product.
 template <int F, bool TRANS>
 __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
-                          int nrhs, int mode, double (*red)[16][17]) {
+                          int nrhs, int mode, double (*red)[16][17], double mul = 1.0) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
   const int kw = nb / 4;
@@ -86,7 +87,7 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     mfma_span<F, TRANS>(M, nb, r0 + c, w * kw, (w + 1) * kw, c < nc ? V + (int64_t)(c0 + c) * ldv : nullptr, lane,
-                        acc0, acc1);
+                        acc0, acc1, mul);
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[w][q + 4 * r][c] = acc0[r] + acc1[r];
     __syncthreads();
@@ -104,14 +105,14 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
 }
 
 template <bool TRANS>
-__device__ void tile_mfma_any(const void* M, int f, int nb, int r0, const double* V, int64_t ldv, double* out,
-                              int64_t ldo, int nrhs, int mode, double (*red)[16][17]) {
+__device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, const double* V, int64_t ldv,
+                              double* out, int64_t ldo, int nrhs, int mode, double (*red)[16][17]) {
   switch (f) {
     case F64: tile_mfma<F64, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
     case F32: tile_mfma<F32, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
     case F16: tile_mfma<F16, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
     case BF16: tile_mfma<BF16, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
-    default: tile_mfma<F8, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
+    default: tile_mfma<F8, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red, mul); break;
   }
 }
 
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* 
   __shared__ double red[4][16][17];
   const int nb = tv.nb, rb = nb / 16;
   const int i = k + 1 + blockIdx.x / rb;
-  tile_mfma_any<false>(tv.tile(i, k), tv.tfmt(i, k), nb, (blockIdx.x % rb) * 16, W + (int64_t)k * nb, ld,
+  tile_mfma_any<false>(tv.tile(i, k), tv.tfmt(i, k), tv.tmul(i, k), nb, (blockIdx.x % rb) * 16, W + (int64_t)k * nb, ld,
                        R + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* 
   __shared__ double red[4][16][17];
   const int nb = tv.nb, rb = nb / 16;
   const int i = blockIdx.x / rb;  // i < k
-  tile_mfma_any<true>(tv.tile(k, i), tv.tfmt(k, i), nb, (blockIdx.x % rb) * 16, X + (int64_t)k * nb, ld,
+  tile_mfma_any<true>(tv.tile(k, i), tv.tfmt(k, i), tv.tmul(k, i), nb, (blockIdx.x % rb) * 16, X + (int64_t)k * nb, ld,
                       V + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* s
   const int nb = tv.nb, n = tv.n;
   void* tile = tv.tile(ti, tj);
   const int f = tv.tfmt(ti, tj);
+  const int sc = f == F8 ? tv.tscale(ti, tj) : 0;  // FP8 tiles hold codes of v 2^sc
   const int c0 = blockIdx.y * 16;
   for (int e = threadIdx.x; e < 16 * nb; e += blockDim.x) {
     int c = c0 + e / nb, r = e % nb;
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* s
       int hi = R > C ? R : C, lo = R > C ? C : R;
       v = src[(int64_t)lo * lds + hi];
     }
-    store_round(tile, f, (int64_t)c * nb + r, v);
+    store_round(tile, f, (int64_t)c * nb + r, f == F8 ? ldexp(v, sc) : v);
     if (sig64) sig64[(int64_t)blockIdx.x * nb * nb + (int64_t)c * nb + r] = v;  // FP64 copy, packed tile order
   }
 }
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(256) void k_tiles_to_dense(TileView tv, double* L, 
     double v = 0.0;
     if (R >= C) {
       int ti = R / nb, r = R % nb;
-      v = load_wide(tv.tile(ti, tj), tv.tfmt(ti, tj), (int64_t)c * nb + r);
+      v = load_wide(tv.tile(ti, tj), tv.tfmt(ti, tj), (int64_t)c * nb + r) * tv.tmul(ti, tj);
     }
     L[(int64_t)C * ldl + R] = v;
   }
@@ -134,6 +135,53 @@ __global__ __launch_bounds__(256) void k_cov_tile_amax(int n, int nb, int nt, co
   if (threadIdx.x == 0) amax[(int64_t)ti * nt + tj] = red[0];
 }
 
+// Largest |A_rc| over the true entries of each lower tile of a dense FP64 matrix
+// (lower triangle read).
+__global__ __launch_bounds__(256) void k_dense_tile_amax(int n, int nb, int nt, const double* A, int64_t lda,
+                                                         double* amax) {
+  int ti, tj;
+  tri_unpack(blockIdx.x, ti, tj);
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += blockDim.x) {
+    int c = (int)(e / nb), r = (int)(e % nb);
+    int R = ti * nb + r, C = tj * nb + c;
+    if (R < n && C < n) {
+      const int hi = R > C ? R : C, lo = R > C ? C : R;
+      m = fmax(m, fabs(A[(int64_t)lo * lda + hi]));
+    }
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) amax[(int64_t)ti * nt + tj] = red[0];
+}
+
+hipError_t launch_dense_tile_amax(int n, int nb, const double* A, int64_t lda, double* amax, hipStream_t s) {
+  int nt = (n + nb - 1) / nb;
+  if (nt == 0) return hipSuccess;
+  k_dense_tile_amax<<<nt * (nt + 1) / 2, 256, 0, s>>>(n, nb, nt, A, lda, amax);
+  return hipGetLastError();
+}
+
+// scale exponent of every FP8 tile from its largest magnitude (0 for the others)
+__global__ void k_fp8_scales(TileView tv, const double* amax) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= tv.nt * (tv.nt + 1) / 2) return;
+  int ti, tj;
+  tri_unpack(t, ti, tj);
+  tv.sc[t] = (int8_t)(tv.fmt[t] == F8 ? fp8_scale_exp(amax[(int64_t)ti * tv.nt + tj]) : 0);
+}
+
+hipError_t launch_fp8_scales(const TileView& tv, const double* amax, hipStream_t s) {
+  const int ntiles = tv.nt * (tv.nt + 1) / 2;
+  k_fp8_scales<<<(ntiles + 255) / 256, 256, 0, s>>>(tv, amax);
+  return hipGetLastError();
+}
+
 hipError_t launch_covariance_tile_amax(int n, int nb, const double* locs, const mpcr_theta_t& th, double* amax,
                                        hipStream_t s) {
   int nt = (n + nb - 1) / nb;
@@ -148,13 +196,6 @@ hipError_t launch_covariance_tile_amax(int n, int nb, const double* locs, const 
 // block, the largest s with max|block| * 2^s <= 448)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int fp8_scale_exponent(double amax) {
-  if (!(amax > 0.0)) return 0;
-  int E;
-  double m = frexp(amax, &E);     // amax = m 2^E, m in [0.5, 1); 448 = 0.875 2^9
-  int s = (m <= 0.875) ? 9 - E : 8 - E;
-  return s < -128 ? -128 : (s > 127 ? 127 : s);
-}
 
 __global__ __launch_bounds__(256) void k_block_scale(int64_t m, int64_t n, const double* src, int64_t lds,
                                                      int8_t* sexp, int64_t bm) {
@@ -171,7 +212,7 @@ __global__ __launch_bounds__(256) void k_block_scale(int64_t m, int64_t n, const
     if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) sexp[bj * bm + bi] = (int8_t)fp8_scale_exponent(red[0]);
+  if (threadIdx.x == 0) sexp[bj * bm + bi] = (int8_t)fp8_scale_exp(red[0]);
 }
 
 __global__ __launch_bounds__(256) void k_convert(int prec, int64_t m, int64_t n, const double* src, int64_t lds,

@@ -5,9 +5,9 @@
   log-likelihood has an O(n) closed form at any n: the FP64 map and the
   65536-site band map (FP64 for d <= 1, FP32 for 2 <= d <= 4, FP16 beyond)
   are checked against it for all 256 right-hand sides.
-* The Matern 5/2 recipe of the 65536-site workload: its band map puts the
-  far tiles in FP8, which the tile factorisation does not hold (rejected with
-  ERR_ARG).  The norm-guarded map with the 32768-site guard (0.01 nugget)
+* The Matern 5/2 recipe of the 65536-site workload: its band map (FP16 from
+  distance 5, FP8 with per-tile scales from 16) makes the stored matrix
+  indefinite (NOT_SPD), like the BF16 band at 32768 sites.  The norm-guarded map with the 32768-site guard (0.01 nugget)
   breaks down on this smoother, larger covariance (NOT_SPD: the FP32-stored
   tiles' perturbation summed over a row of Sigma exceeds its smallest
   eigenvalue), which is checked; with 1e-4 nugget (1651 FP64 / 429 FP32
@@ -41,7 +41,8 @@ def g():
     ctx.close()
 
 
-@pytest.mark.parametrize("bands", [None, ((1, "fp64"), (4, "fp32"), (None, "fp16"))])
+@pytest.mark.parametrize("bands", [None, ((1, "fp64"), (4, "fp32"), (None, "fp16")),
+                                   ((1, "fp64"), (4, "fp32"), (15, "fp16"), (None, "fp8_e4m3"))])
 def test_kms_closed_form_n65536(g, bands):
     gu, ctx = g
     from paper_2406_02701_amd import mpcr
@@ -72,8 +73,9 @@ def test_matern52_n65536_guarded_matches_fp64(g):
     th = gu.theta(W["sigma2"], W["range"], W["nu"], W["nugget"])
     lit = tiled.tilemap_banded(n, nb, ((1, "fp64"), (4, "fp32"), (15, "fp16"), (None, "fp8_e4m3")))
     opts = mpcr.mpcr_refine_opts_t(1e-13, 100, 0, 20, 1)
-    st, _, _ = _loglik(gu, ctx, locs, z, th, nb, lit, order=1, opts=opts)
-    assert st == mpcr.MPCR_ERR_ARG and b"FP8" in mpcr.mpcr_last_error(ctx.ptr)
+    st, _, d = _loglik(gu, ctx, locs, z, th, nb, lit, order=1, opts=opts)
+    print("literal band map:", st, mpcr.mpcr_last_error(ctx.ptr), d.info, flush=True)
+    assert st == mpcr.MPCR_ERR_NOT_SPD and d.info > 0
     # guarded: the band map with FP16 where it had FP8, promoted by the guard
     start = tiled.tilemap_banded(n, nb, ((1, "fp64"), (4, "fp32"), (None, "fp16")))
     loose = gu.guarded_map(ctx, locs, th, n, nb, start, 0.01 * W["nugget"])

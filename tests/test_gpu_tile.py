@@ -211,6 +211,61 @@ def test_mixed_factor_matches_emulation(g, bands):
     mpcr.mpcr_factor_destroy(f)
 
 
+def test_mixed_factor_fp8_tiles_match_emulation(g):
+    """Far tiles in FP8-E4M3 with one power-of-two scale per tile: KMS(0.97) + I
+    (far entries ~1e-4, well inside FP8's range once scaled).  The FP8 tiles
+    hold FP8 values of their own scale and agree with the emulation to the FP8
+    unit roundoff (a different accumulation order flips only isolated FP8
+    roundings; a wrong scale would be off by a factor of two); the other tiles
+    meet the usual factor-level gate."""
+    gu, ctx = g
+    n, nb = 1000, 128
+    A = np.asfortranarray(kms(n, 0.97) + np.eye(n))
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (2, "fp32"), (3, "bf16"), (None, "fp8_e4m3")))
+    f, _ = _factor_dense(gu, ctx, A, nb, m)
+    L = _to_dense(gu, ctx, f, n)
+    emu = tiled.tile_cholesky_emulated(A, nb, m)["L"][:n, :n]
+    nt = m.shape[0]
+    f8 = np.zeros((n, n), bool)
+    for i in range(nt):
+        for j in range(i + 1):
+            sl = (slice(i * nb, min((i + 1) * nb, n)), slice(j * nb, min((j + 1) * nb, n)))
+            t = L[sl]
+            assert np.array_equal(tiled.round_tile(t, int(m[i, j])), t), (i, j)
+            if m[i, j] == ff.CODE["fp8_e4m3"]:
+                f8[sl] = True
+                assert np.linalg.norm(t - emu[sl]) <= 2.0 ** -4 * np.linalg.norm(emu[sl]), (i, j)
+    assert f8.any() and np.abs(L[f8]).max() > 0
+    err = np.linalg.norm(np.where(f8, 0, L - emu)) / np.linalg.norm(np.where(f8, 0, emu))
+    assert err <= 8 * ff.BF16.unit_roundoff * math.sqrt(nt), err
+    from paper_2406_02701_amd import mpcr
+    mpcr.mpcr_factor_destroy(f)
+
+
+def test_loglik_fp8_far_tiles_refines_to_fp64(g):
+    """The log-likelihood path with FP8 far tiles (tile scales from the
+    covariance's tile maxima at generation): the quadratic form refines to the
+    FP64 answer; the log-determinant is that of the mixed factor (not
+    refinable), checked against the emulated mixed factor's."""
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    n, nb = 1536, 128
+    locs = synth.locations(n, 95)
+    z = synth.normal_rhs(n, 2, 96)
+    th = gu.theta(1.0, 0.02, 0.5, 1e-2)
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (3, "fp32"), (None, "fp8_e4m3")))
+    opts = mpcr.mpcr_refine_opts_t(1e-13, 100, 0, 20, 0)
+    st, ll, d = _loglik(gu, ctx, locs, z, th, nb, m, order=1, opts=opts)
+    ctx.check(st)
+    assert d.converged == 1 and d.eta <= 1e-13
+    lo, zo, _ = loglik.order_sites(locs, z)
+    ref = loglik.loglik_plain(lo, zo, 1.0, 0.02, 0.5, 1e-2)
+    assert abs(d.quad0 - ref["quad"][0]) <= 1e-9 * abs(ref["quad"][0])
+    emu = loglik.loglik_mixed(lo, zo, 1.0, 0.02, 0.5, 1e-2, nb, m, tol=1e-13)
+    assert emu["info"] == 0 and abs(emu["logdet"] - ref["logdet"]) > 1e-6  # the FP8 tiles do move it
+    assert abs(d.logdet - emu["logdet"]) <= 1e-2 * abs(emu["logdet"] - ref["logdet"])
+
+
 def test_mixed_refined_solve_reaches_fp64(g):
     gu, ctx = g
     from paper_2406_02701_amd import mpcr
