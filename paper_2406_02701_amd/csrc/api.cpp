@@ -171,6 +171,7 @@ struct mpcr_factor {
   uint8_t* d_fmt = nullptr;
   int* d_info = nullptr;
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles (the panel TRSM's FP64 workspace)
+  double* d_dinv = nullptr;        // nb x 32 doubles: inverted 32 x 32 diagonal blocks of the current L_kk
   double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   double* d_rpart = nullptr;       // partial products of the stored residual
@@ -266,7 +267,7 @@ void free_factor(mpcr_factor* f) {
   DeviceGuard g(f->device);
   for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
                   (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig, (void*)f->d_rpart, (void*)f->d_sc,
-                  (void*)f->d_pamax, (void*)f->d_tamax, (void*)f->d_ws8, (void*)f->d_amax8})
+                  (void*)f->d_pamax, (void*)f->d_tamax, (void*)f->d_ws8, (void*)f->d_amax8, (void*)f->d_dinv})
     dfree(f->arena, p);
   delete f;
 }
@@ -361,6 +362,7 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
       (e = dmalloc(A, &f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(A, &f->d_off, ntiles * 8)) != hipSuccess ||
       (e = dmalloc(A, &f->d_fmt, ntiles)) != hipSuccess || (e = dmalloc(A, &f->d_info, sizeof(int))) != hipSuccess ||
       (e = dmalloc(A, &f->d_trsm_ws, (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 8)) != hipSuccess ||
+      (e = dmalloc(A, &f->d_dinv, (size_t)nb * 32 * 8)) != hipSuccess ||
       (e = dmalloc(A, &f->d_tasks, std::max<size_t>(tasks.size(), 1) * sizeof(GemmTask))) != hipSuccess) {
     free_factor(f);
     return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
@@ -426,9 +428,9 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   for (int64_t k = 0; k < nt; ++k) {
     bool fp8_panel = false;
     for (int64_t i = k + 1; i < nt; ++i) fp8_panel |= (f->map[i * nt + k] == F8);
-    HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, P); }));
+    HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, f->d_dinv, P); }));
     HIP_TRY(ctx, timed(ctx, P, 6, nb3 * (double)(nt - k - 1),
-                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, fp8_panel, P); }));
+                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, f->d_dinv, fp8_panel, P); }));
     if (f->task_cnt[k * 5 + F8] > 0)  // operand scales of the FP8 updates (buffer of this step's parity)
       HIP_TRY(ctx, launch_panel_amax(tv, (int)k, f->d_pamax + (k & 1) * nt, P));
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
@@ -735,6 +737,7 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
   size_t bytes = 0;
   bytes += (size_t)(nt * (nt + 1) / 2) * tile;            // tiles (FP64 bound)
   bytes += (size_t)std::max<int64_t>(nt - 1, 1) * tile;     // TRSM workspace
+  bytes += (size_t)nb * 32 * 8;                             // inverted 32 x 32 diagonal blocks
   bytes += (size_t)nt * tile;                               // inverted diagonal tiles
   bytes += (size_t)solve_bytes(N, nrhs, n);                 // vectors
   bytes += (size_t)n * 24 + (size_t)nt * nt * 16 + 65536;   // sites, permutation, tables

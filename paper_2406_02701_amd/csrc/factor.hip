@@ -705,86 +705,77 @@ __device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B,
 }
 
 // ---------------------------------------------------------------------------
-// Triangular solves on 16-row slabs held in LDS.
+// Triangular solves by one wave with inverted 32 x 32 diagonal blocks.
 //
-// trsm_slab16 solves X L^T = A for 16 rows: A (16 x nc) is the slab S in LDS
-// (row-major, leading dimension nc + 1), L (nc x nc, lower) is read from
-// memory (column-major, leading dimension ldl).  Right-looking over 32-column
-// panels J:
-//   X_J = S_J L_JJ^{-T}          right-looking substitution, two elements of
-//                                 the panel per thread, one barrier per column
-//   S_{>J} -= X_J L_{>J,J}^T     FP64 MFMA, A operand from LDS, B operand
-//                                 straight from L with all loads of a batch
-//                                 in flight before its MFMAs
-// 256 threads; the loops are compact (the kernels that use them run on the
-// factorisation's critical path, where instruction fetch of a long unrolled
-// body would dominate).
+// invert_lower32: the inverse of a 32 x 32 lower-triangular block (column-major,
+// leading dimension ld) into out (32 x 32, column-major); lane c < 32 computes
+// column c by forward substitution on the unit vector e_c (fixed order).
+//
+// trsm_rows16_inv solves X L^T = A for 16 rows r0 .. r0+15 over the columns
+// [c0, c1), left-looking over 32-column chunks J:
+//   T   = A[rows, J] - X[rows, c0:J] L[J, c0:J]^T     (FP64 MFMA)
+//   X_J = T D_J^{-T}                                 (FP64 MFMA, D_J^{-1} given)
+// X (ld ldx) holds the solved columns of these rows, L the factor (ld ldl);
+// load_a(idx) and store_x(idx, v) read A and write X_J at a column-major index
+// of the rows' storage.  Each wave works alone (no barriers): the chunk goes
+// from the MFMA result layout to the operand layout through Ts (16 x 33
+// doubles of LDS per wave), and X is re-read by the same wave after a
+// workgroup-scope fence.
 // ---------------------------------------------------------------------------
-__device__ void trsm_slab16(const double* L, int64_t ldl, int nc, double* S, double (*D)[PW + 1]) {
-  __shared__ double xb[2][16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int sld = nc + 1;
-  const int q = lane >> 4, col = lane & 15;
+__device__ __forceinline__ void invert_lower32(const double* L, int64_t ld, double* out, double (*W)[PW + 1],
+                                               int lane) {
+  for (int e = lane; e < PW * PW; e += 64) {
+    const int r = e % PW, c = e / PW;
+    W[r][c] = r >= c ? L[(int64_t)c * ld + r] : 0.0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < PW) {
+    double y[PW];
+#pragma unroll
+    for (int r = 0; r < PW; ++r) {
+      double v = (r == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < r; ++m) v -= W[r][m] * y[m];
+      y[r] = v / W[r][r];
+    }
+#pragma unroll
+    for (int r = 0; r < PW; ++r) out[lane * PW + r] = y[r];
+  }
+}
+
+template <class LoadA, class StoreX>
+__device__ __forceinline__ void trsm_rows16_inv(const double* X, const double* L, int64_t ld, const double* dinv,
+                                                int c0, int c1, int r0, double (*Ts)[PW + 1], int lane, LoadA load_a,
+                                                StoreX store_x) {
+  const int q = lane >> 4, c = lane & 15;
 #pragma unroll 1
-  for (int J0 = 0; J0 < nc; J0 += PW) {
-    for (int e = tid; e < PW * PW; e += 256) {
-      const int r = e % PW, c = e / PW;
-      D[r][c] = L[(int64_t)(J0 + c) * ldl + J0 + r];
+  for (int J0 = c0; J0 < c1; J0 += PW) {
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    mfma_rows16x32(X, L, ld, r0, J0, c0, J0, lane, acc0, acc1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = q + 4 * r;
+      Ts[R][c] = load_a((int64_t)(J0 + c) * ld + r0 + R) - acc0[r];
+      Ts[R][c + 16] = load_a((int64_t)(J0 + c + 16) * ld + r0 + R) - acc1[r];
     }
-    __syncthreads();
-    // X_J: thread (r, qh) holds columns qh and qh + 16 of row r of the panel;
-    // column c is scaled by its owner, broadcast through LDS (double buffered,
-    // one barrier per column) and eliminated from the columns to its right
-    {
-      const int r = tid & 15, qh = tid >> 4;
-      double s0 = S[r * sld + J0 + qh], s1 = S[r * sld + J0 + qh + 16];
-#pragma unroll 1
-      for (int c = 0; c < PW; ++c) {
-        if (qh == (c & 15)) {
-          const double x = (c < 16 ? s0 : s1) / D[c][c];
-          if (c < 16) s0 = x; else s1 = x;
-          xb[c & 1][r] = x;
-        }
-        __syncthreads();
-        const double xr = xb[c & 1][r];
-        if (qh > c) s0 -= xr * D[qh][c];
-        if (qh + 16 > c) s1 -= xr * D[qh + 16][c];
-      }
-      S[r * sld + J0 + qh] = s0;
-      S[r * sld + J0 + qh + 16] = s1;
+    __builtin_amdgcn_wave_barrier();
+    const double* Di = dinv + (int64_t)(J0 / PW) * PW * PW;  // Di[kk * 32 + n] = D_J^{-1}[n][kk]
+    d4 x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < PW / 4; ++u) {
+      const int kk = 4 * u + q;
+      const double a = Ts[c][kk];
+      x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Di[kk * PW + c], x0, 0, 0, 0);
+      x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Di[kk * PW + 16 + c], x1, 0, 0, 0);
     }
-    __syncthreads();
-    const int ncb = (nc - J0 - PW) / 16;  // 16-column blocks to the right of the panel
-    if (ncb > 0) {
-      double xa[PW / 4];
 #pragma unroll
-      for (int u = 0; u < PW / 4; ++u) xa[u] = S[col * sld + J0 + 4 * u + q];
-      for (int cb0 = wave; cb0 < ncb; cb0 += 4 * 4) {
-        double b[4][PW / 4];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const int cb = cb0 + 4 * h;
-          if (cb < ncb) {
-            const int64_t c = J0 + PW + 16 * cb + col;
-#pragma unroll
-            for (int u = 0; u < PW / 4; ++u) b[h][u] = L[(int64_t)(J0 + 4 * u + q) * ldl + c];
-          }
-        }
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const int cb = cb0 + 4 * h;
-          if (cb < ncb) {
-            d4 acc = {0, 0, 0, 0};
-#pragma unroll
-            for (int u = 0; u < PW / 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], b[h][u], acc, 0, 0, 0);
-            const int c = J0 + PW + 16 * cb + col;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) S[(q + 4 * r) * sld + c] -= acc[r];
-          }
-        }
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i0 = (int64_t)(J0 + c) * ld + r0 + q + 4 * r;
+      store_x(i0, x0[r]);
+      store_x(i0 + 16 * ld, x1[r]);
     }
-    __syncthreads();
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -797,13 +788,14 @@ __device__ void trsm_slab16(const double* L, int64_t ldl, int nc, double* S, dou
 //                      one wave with lane broadcasts, rows below by
 //                      substitution; 16 columns keep the unrolled code small
 //                      enough to stay in the instruction cache),
-//   (b) k_potrf_panel  the rows below solve X D_jj^T = A, 16 rows per
-//                      workgroup (trsm_slab16),
+//                      It also inverts the four 32 x 32 diagonal blocks of
+//                      D_jj into dinv for the solves below,
+//   (b) k_potrf_panel  the rows below solve X D_jj^T = A, one wave per 16
+//                      rows (trsm_rows16_inv),
 //   (c) k_potrf_syrk   the lower trailing part loses L_{:,j} L_{:,j}^T
 //                      (64 x 64 output blocks, FP64 MFMA).
 // ---------------------------------------------------------------------------
 constexpr int SB = 128;
-constexpr int SBLD = SB + 1;
 
 // 64-bit lane broadcast: the value v of lane src, read as a wave-uniform scalar.
 __device__ __forceinline__ double readlane_f64(double v, int src) {
@@ -877,7 +869,7 @@ __device__ __forceinline__ void mfma_rows16x16(const double* A, const double* B,
 
 constexpr int PB = 16;  // panel width inside the diagonal block
 
-__global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j) {
+__global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j, double* dinv) {
   if (*tv.info) return;
   const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
   double* A = (double*)tv.tile(k, k);
@@ -947,27 +939,20 @@ __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j) 
     const int r = e % c1, c = c0 + e / c1;
     if (r < c) A[(int64_t)c * nb + r] = 0.0;
   }
+  // inverses of the four 32 x 32 diagonal blocks, one per wave
+  __shared__ double W[4][PW][PW + 1];
+  const int d0 = c0 + wave * PW;
+  invert_lower32(A + (int64_t)d0 * nb + d0, nb, dinv + (int64_t)d0 * PW, W[wave], lane);
 }
 
-// rows c1 .. nb of block column j: X D_jj^T = A in place, 16 rows per workgroup
-__global__ __launch_bounds__(256) void k_potrf_panel(TileView tv, int k, int j) {
+// rows c1 .. nb of block column j: X D_jj^T = A in place, one wave per 16 rows
+__global__ __launch_bounds__(64) void k_potrf_panel(TileView tv, int k, int j, const double* dinv) {
   if (*tv.info) return;
   const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
   double* A = (double*)tv.tile(k, k);
-  const int r0 = c1 + blockIdx.x * 16;
-  extern __shared__ double smem[];
-  double* S = smem;  // 16 x SBLD
-  double(*D)[PW + 1] = (double(*)[PW + 1])(smem + 16 * SBLD);
-  for (int e = threadIdx.x; e < 16 * SB; e += 256) {
-    const int r = e % 16, c = e / 16;
-    S[r * SBLD + c] = A[(int64_t)(c0 + c) * nb + r0 + r];
-  }
-  __syncthreads();
-  trsm_slab16(A + (int64_t)c0 * nb + c0, nb, SB, S, D);
-  for (int e = threadIdx.x; e < 16 * SB; e += 256) {
-    const int r = e % 16, c = e / 16;
-    A[(int64_t)(c0 + c) * nb + r0 + r] = S[r * SBLD + c];
-  }
+  __shared__ double Ts[16][PW + 1];
+  trsm_rows16_inv(A, A, nb, dinv, c0, c1, c1 + blockIdx.x * 16, Ts, threadIdx.x, [&](int64_t i) { return A[i]; },
+                  [&](int64_t i, double v) { A[i] = v; });
 }
 
 // A[R, C] -= L[R, c0:c1] L[C, c0:c1]^T for c1 <= C <= R < nb; one workgroup per
@@ -994,14 +979,13 @@ __global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
   }
 }
 
-hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
+hipError_t launch_potrf_tile(const TileView& tv, int k, double* dinv, hipStream_t s) {
   const int nsb = tv.nb / SB;
-  const size_t panel_lds = (size_t)(16 * SBLD + PW * (PW + 1)) * sizeof(double);
   for (int j = 0; j < nsb; ++j) {
-    k_potrf_block<<<1, 256, 0, s>>>(tv, k, j);
+    k_potrf_block<<<1, 256, 0, s>>>(tv, k, j, dinv);
     const int rest = (tv.nb - (j + 1) * SB) / 64;  // 64-row blocks below block j
     if (rest > 0) {
-      k_potrf_panel<<<rest * 4, 256, panel_lds, s>>>(tv, k, j);
+      k_potrf_panel<<<rest * 4, 64, 0, s>>>(tv, k, j, dinv);
       k_potrf_syrk<<<rest * (rest + 1) / 2, 256, 0, s>>>(tv, k, j);
     }
   }
@@ -1010,88 +994,27 @@ hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Panel TRSM: for i > k, X = A_ik L_kk^{-T} in FP64, rounded once to p(i,k).
-// k_trsm_slab: one workgroup per 16 rows of a panel tile, the rows widened
-// into an LDS slab and solved there (trsm_slab16).  k_trsm: one workgroup per
-// 64 rows, left-looking over 32-column chunks with the FP64 X kept in a
-// workspace (ws: (nt-k-1) tiles of nb x nb).
+// One wave per 16 rows of a panel tile (trsm_rows16_inv with the inverted
+// diagonal blocks of L_kk from its POTRF); the FP64 X goes to the workspace ws
+// ((nt-k-1) tiles of nb x nb) and the tile receives one rounding of it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trsm_slab(TileView tv, int k) {
+__global__ __launch_bounds__(64) void k_trsm(TileView tv, int k, double* ws, const double* dinv) {
   if (*tv.info) return;
-  const int nb = tv.nb, rs = nb / 16;
-  const int ti = k + 1 + blockIdx.x / rs;
-  const int r0 = (blockIdx.x % rs) * 16;
-  const int sld = nb + 1;
-  extern __shared__ double smem[];
-  double* S = smem;  // 16 x (nb + 1)
-  double(*D)[PW + 1] = (double(*)[PW + 1])(smem + 16 * sld);
-  void* Ap = tv.tile(ti, k);
-  const int fa = tv.tfmt(ti, k);
-  const double ma = tv.tmul(ti, k);
-  for (int e = threadIdx.x; e < 16 * nb; e += 256) {
-    const int r = e % 16, c = e / 16;
-    S[r * sld + c] = load_wide(Ap, fa, (int64_t)c * nb + r0 + r) * ma;
-  }
-  __syncthreads();
-  trsm_slab16((const double*)tv.tile(k, k), nb, nb, S, D);
-  for (int e = threadIdx.x; e < 16 * nb; e += 256) {
-    const int r = e % 16, c = e / 16;
-    store_round(Ap, fa, (int64_t)c * nb + r0 + r, S[r * sld + c]);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_trsm(TileView tv, int k, double* ws) {
-  if (*tv.info) return;
-  const int nb = tv.nb;
-  const int rblocks = nb / 64;
+  const int nb = tv.nb, rblocks = nb / 16;
   const int ti = k + 1 + blockIdx.x / rblocks;
-  const int r0 = (blockIdx.x % rblocks) * 64;
-  const double* Lkk = (const double*)tv.tile(k, k);
+  const int r0 = (blockIdx.x % rblocks) * 16;
   void* Ap = tv.tile(ti, k);
   const int fa = tv.tfmt(ti, k);
-  double* X = ws + (int64_t)(ti - k - 1) * nb * nb;  // column-major nb x nb, rows r0..r0+63 owned here
   const double ma = tv.tmul(ti, k);
-  __shared__ double T[64][PW + 1];
-  __shared__ double D[PW][PW + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  for (int J0 = 0; J0 < nb; J0 += PW) {
-    // T = A[rows, J] - X[rows, :J0] L[J, :J0]^T ; wave w owns rows 16w .. 16w+15
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    mfma_rows16x32(X, Lkk, nb, r0 + wave * 16, J0, 0, J0, lane, acc0, acc1);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int lr = wave * 16 + (lane >> 4) + 4 * r;
-      const int c = lane & 15;
-      T[lr][c] = load_wide(Ap, fa, (int64_t)(J0 + c) * nb + r0 + lr) * ma - acc0[r];
-      T[lr][c + 16] = load_wide(Ap, fa, (int64_t)(J0 + c + 16) * nb + r0 + lr) * ma - acc1[r];
-    }
-    for (int e = tid; e < PW * PW; e += 256) {
-      int r = e % PW, c = e / PW;
-      D[r][c] = Lkk[(int64_t)(J0 + c) * nb + J0 + r];
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double x[PW];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) {
-        double v = T[tid][c];
-#pragma unroll
-        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
-        x[c] = v / D[c][c];
-      }
-#pragma unroll
-      for (int c = 0; c < PW; ++c) X[(int64_t)(J0 + c) * nb + r0 + tid] = x[c];
-    }
-    __syncthreads();
-  }
-  // single rounding into the tile's own format (FP8 tiles: by k_quant_panel_f8,
-  // once the whole tile's largest magnitude is known)
-  if (fa == F8) return;
-  for (int e = tid; e < 64 * nb; e += 256) {
-    int r = e % 64, c = e / 64;
-    int64_t idx = (int64_t)c * nb + r0 + r;
-    store_round(Ap, fa, idx, X[idx]);
-  }
+  double* X = ws + (int64_t)(ti - k - 1) * nb * nb;
+  __shared__ double Ts[16][PW + 1];
+  // FP8 tiles are rounded by k_quant_panel_f8 once the whole tile's largest magnitude is known
+  trsm_rows16_inv(X, (const double*)tv.tile(k, k), nb, dinv, 0, nb, r0, Ts, threadIdx.x,
+                  [&](int64_t i) { return load_wide(Ap, fa, i) * ma; },
+                  [&](int64_t i, double v) {
+                    X[i] = v;
+                    if (fa != F8) store_round(Ap, fa, i, v);
+                  });
 }
 
 // FP8 panel tiles after k_trsm: scale from the solved tile's largest magnitude,
@@ -1116,29 +1039,12 @@ __global__ __launch_bounds__(256) void k_quant_panel_f8(TileView tv, int k, cons
   if (threadIdx.x == 0) tv.sc[tri_index(ti, k)] = (int8_t)sc;
 }
 
-constexpr int TRSM_SLAB_MAX_NB = 1024;  // 16 x (nb + 1) doubles + the 32 x 33 block fit in 160 KiB of LDS
-
-hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, bool fp8_panel, hipStream_t s) {
+hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, const double* dinv, bool fp8_panel,
+                             hipStream_t s) {
   int ntile = tv.nt - k - 1;
   if (ntile <= 0) return hipSuccess;
-  if (fp8_panel) {  // FP8 tiles are rounded after the whole tile is solved
-    k_trsm<<<ntile * (tv.nb / 64), 256, 0, s>>>(tv, k, ws);
-    k_quant_panel_f8<<<ntile, 256, 0, s>>>(tv, k, ws);
-    return hipGetLastError();
-  }
-  // Few panel tiles (the end of the factorisation, where the TRSM is on the
-  // critical path): 16-row slabs give 4x more workgroups and shorter chains.
-  // Many tiles: 64-row workgroups keep the per-step work (and LDS) small.
-  if (tv.nb <= TRSM_SLAB_MAX_NB && ntile * (tv.nb / 16) <= 512) {
-    static hipError_t once = hipFuncSetAttribute(
-        (const void*)k_trsm_slab, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)((16 * (TRSM_SLAB_MAX_NB + 1) + PW * (PW + 1)) * sizeof(double)));
-    if (once != hipSuccess) return once;
-    const size_t lds = (size_t)(16 * (tv.nb + 1) + PW * (PW + 1)) * sizeof(double);
-    k_trsm_slab<<<ntile * (tv.nb / 16), 256, lds, s>>>(tv, k);
-  } else {
-    k_trsm<<<ntile * (tv.nb / 64), 256, 0, s>>>(tv, k, ws);
-  }
+  k_trsm<<<ntile * (tv.nb / 16), 64, 0, s>>>(tv, k, ws, dinv);
+  if (fp8_panel) k_quant_panel_f8<<<ntile, 256, 0, s>>>(tv, k, ws);
   return hipGetLastError();
 }
 

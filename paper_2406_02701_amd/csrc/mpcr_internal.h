@@ -221,7 +221,7 @@ hipError_t launch_covariance_tile_amax(int n, int nb, const double* locs, const 
 hipError_t launch_convert(int prec, int64_t m, int64_t n, const double* src, int64_t lds, void* dst,
                           int64_t ldd, int8_t* scale_exp, hipStream_t s);
 
-hipError_t launch_potrf_tile(const TileView& tv, int k, hipStream_t s);
+hipError_t launch_potrf_tile(const TileView& tv, int k, double* dinv, hipStream_t s);
 // FP8 tiles: per-tile scales from the tile maxima (amax: nt x nt, row-major)
 hipError_t launch_fp8_scales(const TileView& tv, const double* amax, hipStream_t s);
 hipError_t launch_dense_tile_amax(int n, int nb, const double* A, int64_t lda, double* amax, hipStream_t s);
@@ -231,7 +231,8 @@ hipError_t launch_panel_amax(const TileView& tv, int k, double* pamax, hipStream
 // values staged in FP32 (ws32: cnt nb^2 floats, amax32: cnt words), then requantised
 hipError_t launch_tile_update_fp8(const TileView& tv, int k, const GemmTask* tasks, int ntasks, const double* pamax,
                                   float* ws32, unsigned* amax32, hipStream_t s);
-hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, bool fp8_panel, hipStream_t s);
+hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, const double* dinv, bool fp8_panel,
+                             hipStream_t s);
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
                               hipStream_t s);
 hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s);
