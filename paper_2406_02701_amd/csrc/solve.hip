@@ -28,14 +28,16 @@ __device__ __forceinline__ double ldw(const void* p, int64_t i) {
 // The tile products of the solves and residuals are small GEMMs (nb x nb times
 // nb x 16 right-hand sides) done with FP64 MFMA 16x16x4.  They sit on the
 // sequential chain of the sweeps, so they are organised for latency: one
-// workgroup owns 16 output rows, its four waves split the contraction into
-// quarters and add their 16 x 16 partial products through LDS in a fixed
+// workgroup owns 16 output rows, its SW waves split the contraction into
+// equal parts and add their 16 x 16 partial products through LDS in a fixed
 // order.  Both operands are read straight from memory (the tile widened to
 // FP64 on load), eight k4 steps per batch with the next batch's loads issued
 // before the current batch's MFMAs.  Lane l supplies A[row = l % 16][k = l / 16]
 // and B[k = l / 16][c = l % 16]; the result lane l, register r is
 // D[l / 16 + 4 r][l % 16].
 constexpr int MB = 8;  // k4 steps per batch
+constexpr int SW = 8;  // waves per workgroup of the tile products (each nb / SW of the contraction)
+constexpr int STHREADS = 64 * SW;
 
 // acc0/acc1 += op(M)[row, k0 .. k1) * V[k0 .. k1, c], op(M)[row][k] = M[k * ldm + row]
 // (TRANS false) or M[row * ldm + k] (TRANS true); V is this lane's column of
@@ -82,7 +84,7 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
                           int nrhs, int mode, double (*red)[16][17], double mul = 1.0) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
-  const int kw = nb / 4;
+  const int kw = nb / SW;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
@@ -95,7 +97,9 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = q + 4 * r;
-        const double v = ((red[0][rr][c] + red[1][rr][c]) + red[2][rr][c]) + red[3][rr][c];
+        double v = red[0][rr][c];
+#pragma unroll
+        for (int x = 1; x < SW; ++x) v += red[x][rr][c];
         double* o = out + (int64_t)(c0 + c) * ldo + r0 + rr;
         *o = mode == 0 ? v : *o - v;
       }
@@ -117,18 +121,18 @@ __device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, 
 }
 
 // one workgroup per 16 output rows
-__global__ __launch_bounds__(256) void k_fwd_diag(int nb, const double* Linv, int k, const double* R, double* W,
+__global__ __launch_bounds__(STHREADS) void k_fwd_diag(int nb, const double* Linv, int k, const double* R, double* W,
                                                   int64_t ld, int nrhs, const int* info) {
   if (*info) return;
-  __shared__ double red[4][16][17];
+  __shared__ double red[SW][16][17];
   const int64_t off = (int64_t)k * nb;
   tile_mfma<F64, false>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, R + off, ld, W + off, ld, nrhs, 0, red);
 }
 
-__global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
+__global__ __launch_bounds__(STHREADS) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
                                                     int nrhs) {
   if (*tv.info) return;
-  __shared__ double red[4][16][17];
+  __shared__ double red[SW][16][17];
   const int nb = tv.nb, rb = nb / 16;
   const int i = k + 1 + blockIdx.x / rb;
   tile_mfma_any<false>(tv.tile(i, k), tv.tfmt(i, k), tv.tmul(i, k), nb, (blockIdx.x % rb) * 16, W + (int64_t)k * nb, ld,
@@ -136,18 +140,18 @@ __global__ __launch_bounds__(256) void k_fwd_update(TileView tv, int k, double* 
 }
 
 // X_k = Linv_kk^T V_k: the transposed product of the same inverse
-__global__ __launch_bounds__(256) void k_bwd_diag(int nb, const double* Linv, int k, const double* V, double* X,
+__global__ __launch_bounds__(STHREADS) void k_bwd_diag(int nb, const double* Linv, int k, const double* V, double* X,
                                                   int64_t ld, int nrhs, const int* info) {
   if (*info) return;
-  __shared__ double red[4][16][17];
+  __shared__ double red[SW][16][17];
   const int64_t off = (int64_t)k * nb;
   tile_mfma<F64, true>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, V + off, ld, X + off, ld, nrhs, 0, red);
 }
 
-__global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
+__global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
                                                     int nrhs) {
   if (*tv.info) return;
-  __shared__ double red[4][16][17];
+  __shared__ double red[SW][16][17];
   const int nb = tv.nb, rb = nb / 16;
   const int i = blockIdx.x / rb;  // i < k
   tile_mfma_any<true>(tv.tile(k, i), tv.tfmt(k, i), tv.tmul(k, i), nb, (blockIdx.x % rb) * 16, X + (int64_t)k * nb, ld,
@@ -156,25 +160,25 @@ __global__ __launch_bounds__(256) void k_bwd_update(TileView tv, int k, double* 
 
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
                            int nrhs, hipStream_t s) {
-  k_fwd_diag<<<tv.nb / 16, 256, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
+  k_fwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
                              hipStream_t s) {
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
-  k_fwd_update<<<nt * (tv.nb / 16), 256, 0, s>>>(tv, k, R, W, ld, nrhs);
+  k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, W, ld, nrhs);
   return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
                            int nrhs, hipStream_t s) {
-  k_bwd_diag<<<tv.nb / 16, 256, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info);
+  k_bwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info);
   return hipGetLastError();
 }
 hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* X, int64_t ld, int nrhs,
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  k_bwd_update<<<k * (tv.nb / 16), 256, 0, s>>>(tv, k, V, X, ld, nrhs);
+  k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, X, ld, nrhs);
   return hipGetLastError();
 }
 
@@ -304,15 +308,23 @@ hipError_t launch_rowsum_abs_dense(int n, const double* A, int64_t lda, double* 
 // FP64 residual from the stored lower tiles of Sigma, R = B - Sigma X.
 // Streaming pass: one workgroup per stored tile (i, j), j <= i, reads the tile
 // once (64 x 64 pieces staged through LDS, double-buffered, row of pieces by
-// row of pieces) and forms both of its products with FP64 MFMA:
-// P[i][j] = S_ij X_j (in registers along a row of pieces) and, off the
-// diagonal, P[j][i] = S_ij^T X_i (added into the partial block in order of the
-// piece rows; each element has one owner lane) - 16 right-hand sides per pass.  With rowsum it also
-// forms the |S| row and column sums.  A second kernel adds, for every row
-// block a, B_a - sum_b P[a][b] in the order b = 0, 1, ..., nt-1 (and the row
-// sums likewise), so results do not depend on scheduling.
-// Partials: nt x nt blocks of nb x 16 doubles, then nt x nt blocks of nb
-// doubles for the row sums.
+// row of pieces) and forms both of its products with FP64 MFMA, 16
+// right-hand sides per pass:
+//   P[i][j] = S_ij X_j     wave w contracts over columns 16 w .. 16 w + 15 of
+//                          each piece (4 values of X_j per lane and piece) for
+//                          all 64 rows, accumulates along the row of pieces in
+//                          registers and the four waves' sums are added in a
+//                          fixed order at its end;
+//   P[j][i] = S_ij^T X_i   (off the diagonal) wave w owns rows 16 w .. of the
+//                          piece's columns, contracts over all 64 piece rows
+//                          (X_i fixed along the row of pieces) and adds into
+//                          the partial block in order of the piece rows; each
+//                          element has one owner lane.
+// With rowsum it also forms the |S| row and column sums.  A second kernel
+// adds, for every row block a, B_a - sum_b P[a][b] in the order
+// b = 0, 1, ..., nt-1 (and the row sums likewise), so results do not depend on
+// scheduling.  Partials: nt x nt blocks of nb x 16 doubles, then nt x nt
+// blocks of nb doubles for the row sums.
 // ---------------------------------------------------------------------------
 constexpr int RP = 64;        // rows / columns of a staged piece
 constexpr int RPLD = RP + 2;  // LDS leading dimension (doubles) of a piece, [column][row]
@@ -320,6 +332,7 @@ constexpr int RPLD = RP + 2;  // LDS leading dimension (doubles) of a piece, [co
 __global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const double* sig, const double* X, int64_t ld,
                                                          int c0, int nc, double* part, int want_sum) {
   __shared__ __attribute__((aligned(16))) double Sp[2][RP * RPLD];
+  __shared__ double rn[RP][RHS_CHUNK + 1];  // the waves' P[i][j] sums of a row of pieces
   __shared__ double red[4][RP];
   int i = 0, rem = blockIdx.x;  // tile (i, j) from the packed lower index
   while (rem > i) { rem -= i + 1; ++i; }
@@ -337,12 +350,12 @@ __global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const d
   const double* Xj = X + (int64_t)(c0 + (cv ? col : 0)) * ld + (int64_t)j * nb;
   const double* Xi = X + (int64_t)(c0 + (cv ? col : 0)) * ld + (int64_t)i * nb;
 
-  // Everything piece (pr, pc) needs from memory is requested one piece ahead:
-  // the piece itself (thread t: column t / 16 + 16 h, rows 4 (t % 16) .. +3),
-  // this lane's right-hand-side values for both products, and the running
-  // transposed partial it adds to.
+  // Requested one piece ahead: the piece itself (thread t: column t / 16 + 16 h,
+  // rows 4 (t % 16) .. +3), this lane's X_j values for the piece's columns
+  // 16 w .., the running transposed partial it adds to, and at the start of a
+  // row of pieces that row's X_i values.
   double4 ld4[4];
-  double xn[RP / 4], xt[RP / 4], pold[4];
+  double xn[4], pold[4], xtn[RP / 4];
   auto prefetch = [&](int pr, int pc) {
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -350,13 +363,14 @@ __global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const d
       ld4[h] = *(const double4*)(T + (int64_t)(RP * pc + c) * nb + RP * pr + r);
     }
 #pragma unroll
-    for (int u = 0; u < RP / 4; ++u) {
-      xn[u] = cv ? Xj[RP * pc + 4 * u + q] : 0.0;
-      xt[u] = cv ? Xi[RP * pr + 4 * u + q] : 0.0;
-    }
+    for (int u = 0; u < 4; ++u) xn[u] = cv ? Xj[RP * pc + 16 * w + 4 * u + q] : 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       pold[r] = (!diag && cv && pr > 0) ? Pji[(int64_t)col * nb + RP * pc + 16 * w + q + 4 * r] : 0.0;
+    if (pc == 0) {
+#pragma unroll
+      for (int u = 0; u < RP / 4; ++u) xtn[u] = cv ? Xi[RP * pr + 4 * u + q] : 0.0;
+    }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
@@ -373,20 +387,21 @@ __global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const d
 
   prefetch(0, 0);
   sstore(0);
-  double cxn[RP / 4], cxt[RP / 4], cpold[4];
+  double cxn[4], cpold[4], cxt[RP / 4];
 #pragma unroll
-  for (int u = 0; u < RP / 4; ++u) {
-    cxn[u] = xn[u];
-    cxt[u] = xt[u];
-  }
+  for (int u = 0; u < 4; ++u) cxn[u] = xn[u];
+#pragma unroll
+  for (int u = 0; u < RP / 4; ++u) cxt[u] = xtn[u];
 #pragma unroll
   for (int r = 0; r < 4; ++r) cpold[r] = pold[r];
   __syncthreads();
   int cur = 0;
 #pragma unroll 1
   for (int pr = 0; pr < np; ++pr) {
-    d4 accN = {0, 0, 0, 0};  // rows 64 pr + 16 w .. of block i, summed over the column pieces
-    double rs = 0.0;         // |S| row sums of row 64 pr + tid % 64 (columns tid / 64 + 4 m of each piece)
+    d4 accN[4];  // rows 64 pr + 16 a + .. of block i, this wave's quarter of the columns
+#pragma unroll
+    for (int a = 0; a < 4; ++a) accN[a] = d4{0, 0, 0, 0};
+    double rs = 0.0;  // |S| row sums of row 64 pr + tid % 64 (columns tid / 64 + 4 m of each piece)
 #pragma unroll 1
     for (int pc = 0; pc < np; ++pc) {
       const int nxt = pr * np + pc + 1;
@@ -394,9 +409,12 @@ __global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const d
       if (more) prefetch(nxt / np, nxt % np);
       const double* S = Sp[cur];
 #pragma unroll
-      for (int u = 0; u < RP / 4; ++u)  // N: row 64 pr + 16 w + col over the piece's columns
-        accN = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(4 * u + q) * RPLD + 16 * w + col], cxn[u], accN, 0, 0, 0);
-      if (!diag) {  // T: rows 64 pc + 16 w + col of block j over the piece's rows, added to P[j][i] in order of pr
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          accN[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(16 * w + 4 * u + q) * RPLD + 16 * a + col], cxn[u], accN[a],
+                                                         0, 0, 0);
+      if (!diag) {  // rows 64 pc + 16 w + col of block j over the piece's rows, added to P[j][i] in order of pr
         d4 accT = {cpold[0], cpold[1], cpold[2], cpold[3]};
 #pragma unroll
         for (int u = 0; u < RP / 4; ++u)
@@ -422,19 +440,34 @@ __global__ __launch_bounds__(256) void k_residual_stream(int nb, int nt, const d
       if (more) {
         sstore(cur ^ 1);
 #pragma unroll
-        for (int u = 0; u < RP / 4; ++u) {
-          cxn[u] = xn[u];
-          cxt[u] = xt[u];
-        }
+        for (int u = 0; u < 4; ++u) cxn[u] = xn[u];
 #pragma unroll
         for (int r = 0; r < 4; ++r) cpold[r] = pold[r];
+        if (nxt % np == 0) {
+#pragma unroll
+          for (int u = 0; u < RP / 4; ++u) cxt[u] = xtn[u];
+        }
       }
       __syncthreads();
       cur ^= 1;
     }
-    if (cv) {
+    // P[i][j] rows of this row of pieces: ((p3 + p2) + p1) + p0 through rn
+#pragma unroll 1
+    for (int s = 3; s >= 0; --s) {
+      if (w == s) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Pij[(int64_t)col * nb + RP * pr + 16 * w + q + 4 * r] = accN[r];
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rr = 16 * a + q + 4 * r;
+            const double v = s == 3 ? accN[a][r] : accN[a][r] + rn[rr][col];
+            if (s > 0)
+              rn[rr][col] = v;
+            else if (cv)
+              Pij[(int64_t)col * nb + RP * pr + rr] = v;
+          }
+      }
+      __syncthreads();
     }
     if (want_sum) {
       red[tid / 64][tid % 64] = rs;
