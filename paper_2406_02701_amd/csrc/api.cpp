@@ -103,8 +103,9 @@ struct mpcr_ctx {
   double k_ms[NKIND] = {0}, k_flops[NKIND] = {0};
   int64_t k_launches[NKIND] = {0};
   // lookahead: a second stream for the bulk of each trailing update
-  hipStream_t upd = nullptr;
-  std::vector<hipEvent_t> sync_ev;  // timing-disabled events, 2 per step
+  hipStream_t upd = nullptr;        // trailing updates of the factorisation
+  hipStream_t col = nullptr;        // updates of the next panel column
+  std::vector<hipEvent_t> sync_ev;  // timing-disabled events, 3 per step
 };
 
 namespace {
@@ -146,10 +147,11 @@ hipError_t timed(mpcr_ctx* ctx, hipStream_t s, int kind, double flops, F&& launc
 }
 
 hipError_t ensure_lookahead(mpcr_ctx* ctx, size_t nev) {
-  if (!ctx->upd) {
-    hipError_t e = hipStreamCreateWithFlags(&ctx->upd, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-  }
+  for (hipStream_t* st : {&ctx->upd, &ctx->col})
+    if (!*st) {
+      hipError_t e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
   while (ctx->sync_ev.size() < nev) {
     hipEvent_t ev;
     hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -171,8 +173,8 @@ struct mpcr_factor {
   uint8_t* d_fmt = nullptr;
   int* d_info = nullptr;
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles (the panel TRSM's FP64 workspace)
-  double* d_dinv = nullptr;        // nb x 32 doubles: inverted 32 x 32 diagonal blocks of the current L_kk
-  double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles
+  double* d_dinv = nullptr;        // nt x nb x 32 doubles: inverted 32 x 32 diagonal blocks of every L_kk
+  double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles, each stored by rows
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   double* d_rpart = nullptr;       // partial products of the stored residual
   bool linv_ready = false;
@@ -184,7 +186,7 @@ struct mpcr_factor {
   double* d_tamax = nullptr;       // nt x nt tile maxima for the FP8 scales at generation
   float* d_ws8 = nullptr;
   unsigned* d_amax8 = nullptr;
-  int f8_maxP = 0, f8_maxU = 0;    // FP8 output tasks per step on the two streams
+  int f8_maxP = 0, f8_maxU = 0;    // FP8 output tasks per step: next column / the columns after it
   GemmTask* d_tasks = nullptr;
   std::vector<int64_t> task_off;   // [(k * 5 + f)] offset into d_tasks
   std::vector<int> task_cnt;
@@ -362,7 +364,7 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
       (e = dmalloc(A, &f->d_base, (size_t)off)) != hipSuccess || (e = dmalloc(A, &f->d_off, ntiles * 8)) != hipSuccess ||
       (e = dmalloc(A, &f->d_fmt, ntiles)) != hipSuccess || (e = dmalloc(A, &f->d_info, sizeof(int))) != hipSuccess ||
       (e = dmalloc(A, &f->d_trsm_ws, (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 8)) != hipSuccess ||
-      (e = dmalloc(A, &f->d_dinv, (size_t)nb * 32 * 8)) != hipSuccess ||
+      (e = dmalloc(A, &f->d_dinv, (size_t)nt * nb * 32 * 8)) != hipSuccess ||
       (e = dmalloc(A, &f->d_tasks, std::max<size_t>(tasks.size(), 1) * sizeof(GemmTask))) != hipSuccess) {
     free_factor(f);
     return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
@@ -382,38 +384,46 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
   return MPCR_OK;
 }
 
-// Queues the whole right-looking factorisation of an already filled tile store.
-// Queues the right-looking factorisation with a depth-1 lookahead.  The
-// context's stream P carries the critical path: POTRF(k), TRSM(k), then the
-// update of column k+1 (so POTRF(k+1) can start at once); the second stream U
-// carries the rest of step k's trailing update.  U waits for TRSM(k) before
-// its part of step k; P waits for U's step k-1 only before it updates column
-// k+1 in step k, so POTRF(k) and TRSM(k) overlap U's step k-1.
+// Queues the right-looking factorisation of an already filled tile store with
+// a depth-1 lookahead over three streams.  The context's stream P carries the
+// critical path: POTRF(k), TRSM(k), then the SYRK of the next diagonal tile
+// (k+1, k+1), so POTRF(k+1) can start at once.  Stream C updates the rest of
+// column k+1 (the next panel) from panel k while POTRF(k+1) runs; P waits for
+// it before TRSM(k+1).  Stream U carries the rest of step k's trailing update
+// (columns k+2 ..).  U and C wait for TRSM(k); P and C wait for U's step k-1
+// before they touch column k+1, which that step also updates.
 int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   hipStream_t P = ctx->stream;
   TileView tv = f->view();
   f->linv_ready = false;
   const double nb3 = (double)f->nb * f->nb * f->nb;
   const int64_t nt = f->nt;
-  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(2 * nt + 2)));
-  hipStream_t U = ctx->upd;
-  auto ev = [&](int64_t i) { return ctx->sync_ev[i]; };
-  // U starts after everything queued on P so far (the tile fill)
+  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(3 * nt + 2)));
+  hipStream_t U = ctx->upd, C = ctx->col;
+  auto ev = [&](int64_t i) { return ctx->sync_ev[i]; };      // 2k: TRSM(k) done (P), 2k+1: U's step k done
+  auto evc = [&](int64_t k) { return ctx->sync_ev[2 * nt + 2 + k]; };  // C's column k+1 done
+  // U and C start after everything queued on P so far (the tile fill)
   HIP_TRY(ctx, hipEventRecord(ev(2 * nt), P));
   HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * nt), 0));
+  HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * nt), 0));
   static const int order[5] = {F64, F32, BF16, F16, F8};
   const int64_t nb2 = f->nb * f->nb;
-  auto launch_updates = [&](int64_t k, hipStream_t s, bool next_col) -> int {
+  // which: 0 = the SYRK of the next diagonal tile, 1 = the rest of the next
+  // column, 2 = the columns after it
+  auto launch_updates = [&](int64_t k, hipStream_t s, int which) -> int {
     for (int p : order) {
       const int all = f->task_cnt[k * 5 + p], nx = f->task_cnt_next[k * 5 + p];
-      const int cnt = next_col ? nx : all - nx;
-      if (!cnt) continue;
-      const GemmTask* t = f->d_tasks + f->task_off[k * 5 + p] + (next_col ? 0 : nx);
+      // the next column's tasks come first, its diagonal tile (FP64) first among them
+      const int nd = (p == F64 && nx > 0) ? 1 : 0;
+      const int off = which == 0 ? 0 : which == 1 ? nd : nx;
+      const int cnt = which == 0 ? nd : which == 1 ? nx - nd : all - nx;
+      if (cnt <= 0) continue;
+      const GemmTask* t = f->d_tasks + f->task_off[k * 5 + p] + off;
       // GEMM tiles count 2 nb^3, the SYRK (diagonal) tiles nb^3
-      const double ndiag = (p == F64) ? (next_col ? 1.0 : (double)(nt - k - 2)) : 0.0;
+      const double ndiag = (p == F64) ? (which == 0 ? 1.0 : which == 1 ? 0.0 : (double)(nt - k - 2)) : 0.0;
       const double fl = nb3 * (2.0 * cnt - ndiag);
       if (p == F8) {  // each stream stages in its own part of the FP8 workspace
-        const int base = next_col ? 0 : f->f8_maxP;
+        const int base = which == 2 ? f->f8_maxP : 0;
         const double* pamax = f->d_pamax + (k & 1) * nt;
         HIP_TRY(ctx, timed(ctx, s, p, fl, [&] {
           return launch_tile_update_fp8(tv, (int)k, t, cnt, pamax, f->d_ws8 + (int64_t)base * nb2, f->d_amax8 + base, s);
@@ -428,19 +438,25 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   for (int64_t k = 0; k < nt; ++k) {
     bool fp8_panel = false;
     for (int64_t i = k + 1; i < nt; ++i) fp8_panel |= (f->map[i * nt + k] == F8);
-    HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, f->d_dinv, P); }));
+    HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, f->d_dinv + k * f->nb * 32, P); }));
+    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, evc(k - 1), 0));  // column k updated by C
     HIP_TRY(ctx, timed(ctx, P, 6, nb3 * (double)(nt - k - 1),
-                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, f->d_dinv, fp8_panel, P); }));
+                       [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, f->d_dinv + k * f->nb * 32, fp8_panel, P); }));
     if (f->task_cnt[k * 5 + F8] > 0)  // operand scales of the FP8 updates (buffer of this step's parity)
       HIP_TRY(ctx, launch_panel_amax(tv, (int)k, f->d_pamax + (k & 1) * nt, P));
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
     if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
-    if ((rc = launch_updates(k, P, true)) != MPCR_OK) return rc;
+    if ((rc = launch_updates(k, P, 0)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * k), 0));
+    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * (k - 1) + 1), 0));
+    if ((rc = launch_updates(k, C, 1)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, hipEventRecord(evc(k), C));
     HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * k), 0));
-    if ((rc = launch_updates(k, U, false)) != MPCR_OK) return rc;
+    if ((rc = launch_updates(k, U, 2)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipEventRecord(ev(2 * k + 1), U));
   }
   HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * nt - 1), 0));  // join
+  HIP_TRY(ctx, hipStreamWaitEvent(P, evc(nt - 1), 0));
   return MPCR_OK;
 }
 
@@ -460,7 +476,7 @@ int ensure_linv(mpcr_ctx* ctx, mpcr_factor* f) {
   if (!f->d_Linv) HIP_TRY(ctx, dmalloc(f->arena, &f->d_Linv, (size_t)f->nt * f->nb * f->nb * 8));
   const double nb3 = (double)f->nb * f->nb * f->nb;
   HIP_TRY(ctx, timed(ctx, ctx->stream, 7, nb3 / 3.0 * (double)f->nt,
-                     [&] { return launch_trtri_diag(f->view(), f->d_Linv, ctx->stream); }));
+                     [&] { return launch_trtri_diag(f->view(), f->d_Linv, f->d_dinv, ctx->stream); }));
   f->linv_ready = true;
   return MPCR_OK;
 }
@@ -737,7 +753,7 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
   size_t bytes = 0;
   bytes += (size_t)(nt * (nt + 1) / 2) * tile;            // tiles (FP64 bound)
   bytes += (size_t)std::max<int64_t>(nt - 1, 1) * tile;     // TRSM workspace
-  bytes += (size_t)nb * 32 * 8;                             // inverted 32 x 32 diagonal blocks
+  bytes += (size_t)nt * nb * 32 * 8;                        // inverted 32 x 32 diagonal blocks
   bytes += (size_t)nt * tile;                               // inverted diagonal tiles
   bytes += (size_t)solve_bytes(N, nrhs, n);                 // vectors
   bytes += (size_t)n * 24 + (size_t)nt * nt * 16 + 65536;   // sites, permutation, tables
@@ -790,6 +806,7 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto& e : ctx->sync_ev) (void)hipEventDestroy(e);
     if (ctx->upd) (void)hipStreamDestroy(ctx->upd);
+    if (ctx->col) (void)hipStreamDestroy(ctx->col);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;

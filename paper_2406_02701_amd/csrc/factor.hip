@@ -1077,64 +1077,27 @@ hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Inverse of every diagonal tile, Linv_kk = L_kk^{-1} (lower, FP64), used by the
-// tile solves.  One workgroup per (tile, 32-column block J): block column J of
-// the inverse is the forward substitution L X = E_J, swept down the 32-row
-// blocks: X_IJ = D_I^{-1} (E_IJ - sum_{J <= M < I} L_IM X_MJ).
-// Linv holds nt tiles, nb x nb column-major.
+// Inverted diagonal tiles for the solves.  Row r of X = L_kk^{-T} (X L^T = I) is
+// column r of L_kk^{-1}, so trsm_rows16_inv applied to the identity, one wave
+// per 16 rows, gives L_kk^{-1} stored by rows (its transpose in column-major
+// order) from the 32 x 32 block inverses that the tile's POTRF left in dinv;
+// entries left of the rows' own 32-column chunk are zero.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trtri(TileView tv, double* Linv) {
+__global__ __launch_bounds__(64) void k_trtri(TileView tv, double* Linv, const double* dinv) {
   if (*tv.info) return;
-  const int nb = tv.nb, nbl = nb / PW;
-  const int kt = blockIdx.x / nbl;
-  const int J = blockIdx.x % nbl, J0 = J * PW;
-  const double* L = (const double*)tv.tile(kt, kt);
+  const int nb = tv.nb, rb = nb / 16;
+  const int kt = blockIdx.x / rb, r0 = (blockIdx.x % rb) * 16;
+  const int c0 = (r0 / PW) * PW;
   double* X = Linv + (int64_t)kt * nb * nb;
-  __shared__ double T[PW][PW + 1];
-  __shared__ double D[PW][PW + 1];
-  const int tid = threadIdx.x;
-  const int orow = tid % PW, ocol0 = (tid / PW) * 4;  // each thread: 1 row x 4 columns of the block
-
-  // zero the strictly upper part of block column J
-  for (int e = tid; e < J0 * PW; e += 256) {
-    int r = e % J0, c = e / J0;
-    X[(int64_t)(J0 + c) * nb + r] = 0.0;
-  }
-  for (int I0 = J0; I0 < nb; I0 += PW) {
-    double acc[4] = {0, 0, 0, 0};
-    for (int m = J0; m < I0; ++m) {
-      double l = L[(int64_t)m * nb + I0 + orow];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += l * X[(int64_t)(J0 + ocol0 + q) * nb + m];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double e = (I0 == J0 && orow == ocol0 + q) ? 1.0 : 0.0;
-      T[orow][ocol0 + q] = e - acc[q];
-    }
-    for (int e = tid; e < PW * PW; e += 256) {
-      int r = e % PW, c = e / PW;
-      D[r][c] = L[(int64_t)(I0 + c) * nb + I0 + r];
-    }
-    __syncthreads();
-    if (tid < PW) {  // column tid of the block: D x = t
-      double x[PW];
-#pragma unroll
-      for (int r = 0; r < PW; ++r) {
-        double v = T[r][tid];
-#pragma unroll
-        for (int m = 0; m < r; ++m) v -= D[r][m] * x[m];
-        x[r] = v / D[r][r];
-      }
-#pragma unroll
-      for (int r = 0; r < PW; ++r) X[(int64_t)(J0 + tid) * nb + I0 + r] = x[r];
-    }
-    __syncthreads();
-  }
+  __shared__ double Ts[16][PW + 1];
+  const int lane = threadIdx.x;
+  for (int e = lane; e < 16 * c0; e += 64) X[(int64_t)(e / 16) * nb + r0 + e % 16] = 0.0;
+  trsm_rows16_inv(X, (const double*)tv.tile(kt, kt), nb, dinv + (int64_t)kt * nb * PW, c0, nb, r0, Ts, lane,
+                  [&](int64_t i) { return (i % nb) == (i / nb) ? 1.0 : 0.0; }, [&](int64_t i, double v) { X[i] = v; });
 }
 
-hipError_t launch_trtri_diag(const TileView& tv, double* Linv, hipStream_t s) {
-  k_trtri<<<tv.nt * (tv.nb / PW), 256, 0, s>>>(tv, Linv);
+hipError_t launch_trtri_diag(const TileView& tv, double* Linv, const double* dinv, hipStream_t s) {
+  k_trtri<<<tv.nt * (tv.nb / 16), 64, 0, s>>>(tv, Linv, dinv);
   return hipGetLastError();
 }
 

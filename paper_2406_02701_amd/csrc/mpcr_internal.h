@@ -236,7 +236,7 @@ hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, const double
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
                               hipStream_t s);
 hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s);
-hipError_t launch_trtri_diag(const TileView& tv, double* Linv, hipStream_t s);
+hipError_t launch_trtri_diag(const TileView& tv, double* Linv, const double* dinv, hipStream_t s);
 
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W,
                            int64_t ld, int nrhs, hipStream_t s);

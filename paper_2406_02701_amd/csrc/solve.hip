@@ -2,7 +2,7 @@
 //
 // Forward solve L W = B and backward solve L^T X = W over the tile factor (the
 // paper's forwardsolve / backsolve pair of the MLE section), with the inverted
-// FP64 diagonal tiles:
+// FP64 diagonal tiles (each stored by rows, i.e. Linv_kk^T in column-major order):
 //   forward,  k = 0 .. nt-1:  W_k = Linv_kk R_k ;  R_i -= L_ik W_k   (i > k)
 //   backward, k = nt-1 .. 0:  X_k = Linv_kk^T V_k ; V_i -= L_ki^T X_k (i < k)
 // Off-diagonal tiles are read in their storage format and widened to FP64.
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(STHREADS) void k_fwd_diag(int nb, const double* Lin
   if (*info) return;
   __shared__ double red[SW][16][17];
   const int64_t off = (int64_t)k * nb;
-  tile_mfma<F64, false>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, R + off, ld, W + off, ld, nrhs, 0, red);
+  tile_mfma<F64, true>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, R + off, ld, W + off, ld, nrhs, 0, red);
 }
 
 __global__ __launch_bounds__(STHREADS) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
@@ -139,13 +139,13 @@ __global__ __launch_bounds__(STHREADS) void k_fwd_update(TileView tv, int k, dou
                        R + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
-// X_k = Linv_kk^T V_k: the transposed product of the same inverse
+// X_k = Linv_kk^T V_k: the stored (row-major) inverse read as column-major
 __global__ __launch_bounds__(STHREADS) void k_bwd_diag(int nb, const double* Linv, int k, const double* V, double* X,
                                                   int64_t ld, int nrhs, const int* info) {
   if (*info) return;
   __shared__ double red[SW][16][17];
   const int64_t off = (int64_t)k * nb;
-  tile_mfma<F64, true>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, V + off, ld, X + off, ld, nrhs, 0, red);
+  tile_mfma<F64, false>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, V + off, ld, X + off, ld, nrhs, 0, red);
 }
 
 __global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
