@@ -43,8 +43,8 @@ PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2516.6, 3: 2516.6, 4: 5033.2}
 FMT_NAME = {0: "fp64", 1: "fp32", 2: "fp16", 3: "bf16", 4: "fp8_e4m3"}
 KIND_NAME = {0: "tile_update_fp64", 1: "tile_update_fp32", 2: "tile_update_fp16", 3: "tile_update_bf16",
              4: "tile_update_fp8", 5: "potrf_fp64", 6: "trsm_fp64", 7: "trtri_diag_fp64", 8: "tile_solve_sweeps",
-             9: "residual_fp64"}
-NKIND = 10
+             9: "residual_fp64", 10: "syrk_next_diag_fp64"}
+NKIND = 11
 
 
 def parse():
@@ -349,7 +349,7 @@ def main():
     fl_per_launch = kfl / max(launches, 1)
     achieved = fl_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     peak = PEAK_TFLOPS[dom] if dom <= 4 else PEAK_TFLOPS[0]
-    bound = "mfma" if dom <= 7 else "alu"
+    bound = "mfma" if dom <= 7 or dom == 10 else "alu"
     roofline = {"bound": bound, "kernel": KIND_NAME[dom], "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": measured_traffic(KIND_NAME[dom]), "traffic_unit": "bytes per launch",
                 "launches": launches, "avg_launch_ms": avg_ms, "flops_per_launch": fl_per_launch}

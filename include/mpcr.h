@@ -142,7 +142,9 @@ const char* mpcr_version(void);
  * Kinds: 0..4 = tile GEMM/SYRK update computed in format MPCR_FP64..FP8,
  * 5 = diagonal POTRF, 6 = panel TRSM, 7 = inversion of the diagonal tiles,
  * 8 = one tile solve (forward and backward sweeps, timed as a whole),
- * 9 = FP64 residual b - Sigma x.  mpcr_ctx_kernel_stats returns, for one
+ * 9 = FP64 residual b - Sigma x, 10 = SYRK of the next diagonal tile from an
+ * FP64 panel tile (on the critical path; kind 0 counts it otherwise).
+ * mpcr_ctx_kernel_stats returns, for one
  * kind, the total milliseconds, the number of launches (sweeps for kind 8)
  * and the algorithmic flops they performed (2 nb^3 per GEMM tile, nb^3 per
  * SYRK or TRSM tile, nb^3/3 per POTRF or inversion, 2 N^2 nrhs per sweep,

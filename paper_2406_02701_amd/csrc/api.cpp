@@ -77,7 +77,7 @@ size_t Arena::in_use() {
 }
 }  // namespace mpcr
 
-constexpr int NKIND = 10;  // kernel kinds timed by the context (see mpcr_ctx_kernel_stats)
+constexpr int NKIND = 11;  // kernel kinds timed by the context (see mpcr_ctx_kernel_stats)
 
 struct mpcr_ctx {
   int device = 0;
@@ -428,6 +428,8 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
         HIP_TRY(ctx, timed(ctx, s, p, fl, [&] {
           return launch_tile_update_fp8(tv, (int)k, t, cnt, pamax, f->d_ws8 + (int64_t)base * nb2, f->d_amax8 + base, s);
         }));
+      } else if (which == 0 && f->map[(k + 1) * nt + k] == F64) {
+        HIP_TRY(ctx, timed(ctx, s, 10, fl, [&] { return launch_syrk_tile(tv, (int)k, (int)k + 1, s); }));
       } else {
         HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s); }));
       }

@@ -867,6 +867,42 @@ __device__ __forceinline__ void mfma_rows16x16(const double* A, const double* B,
                                                acc, 0, 0, 0);
 }
 
+// acc[h] += A[R0 .. R0+15, K0:K1] * B[C0 + 16h .. C0 + 16h + 15, K0:K1]^T, h < 4,
+// straight from column-major FP64 storage (leading dimension ld), 16 k per
+// batch with the next batch's loads in flight.  K1 - K0 is a multiple of 16.
+__device__ __forceinline__ void mfma_rows16x64(const double* A, const double* B, int64_t ld, int R0, int C0, int K0,
+                                               int K1, int lane, d4 (&acc)[4]) {
+  const int r = lane & 15, q = lane >> 4;
+  auto ld20 = [&](int kk, double* a, double (*b)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t col = kk + 4 * u + q;
+      a[u] = A[col * ld + R0 + r];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) b[h][u] = B[col * ld + C0 + 16 * h + r];
+    }
+  };
+  double a[4], b[4][4];
+  ld20(K0, a, b);
+  for (int kk = K0; kk < K1; kk += 16) {
+    double na[4], nbv[4][4];
+    const bool more = kk + 16 < K1;
+    if (more) ld20(kk + 16, na, nbv);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[h][u], acc[h], 0, 0, 0);
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = na[u];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) b[h][u] = nbv[h][u];
+      }
+    }
+  }
+}
+
 constexpr int PB = 16;  // panel width inside the diagonal block
 
 __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j, double* dinv) {
@@ -966,17 +1002,50 @@ __global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
   const int bj = rem;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R0 = c1 + bi * 64 + wave * 16, C0 = c1 + bj * 64;
+  d4 acc[4];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    mfma_rows16x32(A, A, nb, R0, C0 + 32 * h, c0, c1, lane, acc0, acc1);
+  for (int h = 0; h < 4; ++h) acc[h] = d4{0, 0, 0, 0};
+  mfma_rows16x64(A, A, nb, R0, C0, c0, c1, lane, acc);
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 32 * h + (lane & 15);
-      if (R >= C) A[(int64_t)C * nb + R] -= acc0[r];
-      if (R >= C + 16) A[(int64_t)(C + 16) * nb + R] -= acc1[r];
+      const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 16 * h + (lane & 15);
+      if (R >= C) A[(int64_t)C * nb + R] -= acc[h][r];
     }
-  }
+}
+
+// A_jj -= L_jk L_jk^T for one diagonal tile with an FP64 panel tile (the SYRK
+// on the factorisation's critical path): one workgroup per lower 64 x 64 block,
+// wave w: rows 16w .. 16w+15 of the block in one pass over k, FP64 MFMA
+// straight from the tiles.
+__global__ __launch_bounds__(256) void k_syrk_tile(TileView tv, int k, int j) {
+  if (*tv.info) return;
+  const int nb = tv.nb;
+  int bi = 0, rem = blockIdx.x;
+  while (rem > bi) { rem -= bi + 1; ++bi; }
+  const int bj = rem;
+  const double* L = (const double*)tv.tile(j, k);
+  double* A = (double*)tv.tile(j, j);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R0 = bi * 64 + wave * 16, C0 = bj * 64;
+  d4 acc[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) acc[h] = d4{0, 0, 0, 0};
+  mfma_rows16x64(L, L, nb, R0, C0, 0, nb, lane, acc);
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 16 * h + (lane & 15);
+      if (R >= C) A[(int64_t)C * nb + R] -= acc[h][r];
+    }
+}
+
+hipError_t launch_syrk_tile(const TileView& tv, int k, int j, hipStream_t s) {
+  const int nbk = tv.nb / 64;
+  k_syrk_tile<<<nbk * (nbk + 1) / 2, 256, 0, s>>>(tv, k, j);
+  return hipGetLastError();
 }
 
 hipError_t launch_potrf_tile(const TileView& tv, int k, double* dinv, hipStream_t s) {

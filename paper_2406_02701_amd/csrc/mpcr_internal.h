@@ -222,6 +222,8 @@ hipError_t launch_convert(int prec, int64_t m, int64_t n, const double* src, int
                           int64_t ldd, int8_t* scale_exp, hipStream_t s);
 
 hipError_t launch_potrf_tile(const TileView& tv, int k, double* dinv, hipStream_t s);
+// A_jj -= L_jk L_jk^T for an FP64 panel tile (j, k)
+hipError_t launch_syrk_tile(const TileView& tv, int k, int j, hipStream_t s);
 // FP8 tiles: per-tile scales from the tile maxima (amax: nt x nt, row-major)
 hipError_t launch_fp8_scales(const TileView& tv, const double* amax, hipStream_t s);
 hipError_t launch_dense_tile_amax(int n, int nb, const double* A, int64_t lda, double* amax, hipStream_t s);
