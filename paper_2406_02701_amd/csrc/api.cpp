@@ -488,6 +488,7 @@ struct SolveBufs {
   int64_t N = 0, nrhs = 0;
   double *B = nullptr, *X = nullptr, *W = nullptr, *R = nullptr, *V = nullptr;  // N x nrhs each
   double *P = nullptr, *Q = nullptr, *Z = nullptr;
+  double* S = nullptr;  // one solved block by rows (N x nrhs reserved)
   double *scal = nullptr;  // small per-column scalars
   double *partial = nullptr;
   int* active = nullptr;
@@ -496,7 +497,7 @@ struct SolveBufs {
 int64_t solve_bytes(int64_t N, int64_t nrhs, int64_t n) {
   int64_t blk = N * nrhs * 8;
   int64_t nslab = (n + 1023) / 1024 + 1;
-  return 8 * blk + 16 * nrhs * 8 + nslab * nrhs * 5 * 8 + nrhs * 4 + 4096;
+  return 9 * blk + 16 * nrhs * 8 + nslab * nrhs * 5 * 8 + nrhs * 4 + 4096;
 }
 
 int carve(mpcr_ctx* ctx, int64_t N, int64_t nrhs, int64_t n, SolveBufs& b) {
@@ -512,7 +513,7 @@ int carve(mpcr_ctx* ctx, int64_t N, int64_t nrhs, int64_t n, SolveBufs& b) {
   int64_t blk = N * nrhs * 8;
   b.N = N;
   b.nrhs = nrhs;
-  double** blocks[8] = {&b.B, &b.X, &b.W, &b.R, &b.V, &b.P, &b.Q, &b.Z};
+  double** blocks[9] = {&b.B, &b.X, &b.W, &b.R, &b.V, &b.P, &b.Q, &b.Z, &b.S};
   for (auto bp : blocks) {
     *bp = (double*)p;
     p += blk;
@@ -523,7 +524,7 @@ int carve(mpcr_ctx* ctx, int64_t N, int64_t nrhs, int64_t n, SolveBufs& b) {
   b.partial = (double*)p;
   p += nslab * nrhs * 5 * 8;
   b.active = (int*)p;
-  HIP_TRY(ctx, launch_fill(ctx->ws_vec, 8 * N * nrhs, 0.0, ctx->stream));
+  HIP_TRY(ctx, launch_fill(ctx->ws_vec, 9 * N * nrhs, 0.0, ctx->stream));
   return MPCR_OK;
 }
 
@@ -540,14 +541,14 @@ int tile_solve(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const double* Bsrc, 
     // b.V is the working copy of both sweeps, so Bsrc may be any other block
     hipError_t r = launch_copy_cols((int)f->N, nrhs, Bsrc, ld, b.V, ld, s);
     for (int64_t k = 0; k < f->nt && r == hipSuccess; ++k) {
-      r = launch_fwd_diag(tv, f->d_Linv, (int)k, b.V, Wdst, ld, nrhs, s);
-      if (r == hipSuccess) r = launch_fwd_update(tv, (int)k, b.V, Wdst, ld, nrhs, s);
+      r = launch_fwd_diag(tv, f->d_Linv, (int)k, b.V, Wdst, ld, nrhs, b.S, s);
+      if (r == hipSuccess) r = launch_fwd_update(tv, (int)k, b.V, b.S, ld, nrhs, s);
     }
     if (!backward || r != hipSuccess) return r;
     r = launch_copy_cols((int)f->N, nrhs, Wdst, ld, b.V, ld, s);
     for (int64_t k = f->nt - 1; k >= 0 && r == hipSuccess; --k) {
-      r = launch_bwd_diag(tv, f->d_Linv, (int)k, b.V, Xdst, ld, nrhs, s);
-      if (r == hipSuccess) r = launch_bwd_update(tv, (int)k, b.V, Xdst, ld, nrhs, s);
+      r = launch_bwd_diag(tv, f->d_Linv, (int)k, b.V, Xdst, ld, nrhs, b.S, s);
+      if (r == hipSuccess) r = launch_bwd_update(tv, (int)k, b.V, b.S, ld, nrhs, s);
     }
     return r;
   });

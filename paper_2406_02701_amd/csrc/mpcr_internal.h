@@ -240,13 +240,16 @@ hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTas
 hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s);
 hipError_t launch_trtri_diag(const TileView& tv, double* Linv, const double* dinv, hipStream_t s);
 
+// One step of the tile sweeps: the diag launch solves block k (and writes it
+// by rows into stage, nb x nrhs), the update launch subtracts its product from
+// the remaining blocks, reading the right-hand side from stage.
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W,
-                           int64_t ld, int nrhs, hipStream_t s);
-hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
+                           int64_t ld, int nrhs, double* stage, hipStream_t s);
+hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* stage, int64_t ld, int nrhs,
                              hipStream_t s);
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* X,
-                           int64_t ld, int nrhs, hipStream_t s);
-hipError_t launch_bwd_update(const TileView& tv, int k, double* R, const double* X, int64_t ld, int nrhs,
+                           int64_t ld, int nrhs, double* stage, hipStream_t s);
+hipError_t launch_bwd_update(const TileView& tv, int k, double* R, const double* stage, int64_t ld, int nrhs,
                              hipStream_t s);
 
 // R = B - Sigma X (B == NULL: R = -Sigma X); rowsum != NULL also receives sum_c |Sigma_rc|

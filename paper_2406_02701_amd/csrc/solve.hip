@@ -41,11 +41,12 @@ constexpr int STHREADS = 64 * SW;
 
 // acc0/acc1 += op(M)[row, k0 .. k1) * V[k0 .. k1, c], op(M)[row][k] = M[k * ldm + row]
 // (TRANS false) or M[row * ldm + k] (TRANS true); V is this lane's column of
-// the right-hand side (NULL: zero).  k1 - k0 is a multiple of 4; the k4 steps
-// of a batch past k1 read nothing and multiply zeros.
+// the right-hand side (element k at V[k * vsk]; NULL: zero).  k1 - k0 is a
+// multiple of 4; the k4 steps of a batch past k1 read nothing and multiply
+// zeros.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t row, int k0, int k1, const double* V,
-                                          int lane, d4& acc0, d4& acc1, double mul = 1.0) {
+                                          int64_t vsk, int lane, d4& acc0, d4& acc1, double mul = 1.0) {
   const int q = lane >> 4;
   double a[MB], b[MB], an[MB], bn[MB];
   auto load = [&](int kk, double* da, double* db) {
@@ -55,7 +56,7 @@ __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t ro
       const bool in = kk + 4 * u < k1;
       da[u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
       if constexpr (F == F8) da[u] *= mul;  // FP8 tiles hold codes of v 2^s
-      db[u] = (V && in) ? V[k] : 0.0;
+      db[u] = (V && in) ? V[k * vsk] : 0.0;
     }
   };
   load(k0, a, b);
@@ -78,18 +79,21 @@ __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t ro
 }
 
 // out[r0 .. r0+15][c] (op)= sum_k op(M)[r0 + .., k] V[k][c] over one nb x nb tile M
-// (format F, column-major); mode 0: out = product, mode 1: out -= product.
+// (format F, column-major); V[k][c] at V[k * vsk + c * vsc]; mode 0:
+// out = product, mode 1: out -= product.  With copy (mode 0), the result is
+// also written by rows: copy[row * nrhs + c].
 template <int F, bool TRANS>
-__device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_t ldv, double* out, int64_t ldo,
-                          int nrhs, int mode, double (*red)[16][17], double mul = 1.0) {
+__device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_t vsc, int64_t vsk, double* out,
+                          int64_t ldo, int nrhs, int mode, double (*red)[16][17], double mul = 1.0,
+                          double* copy = nullptr) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
   const int kw = nb / SW;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    mfma_span<F, TRANS>(M, nb, r0 + c, w * kw, (w + 1) * kw, c < nc ? V + (int64_t)(c0 + c) * ldv : nullptr, lane,
-                        acc0, acc1, mul);
+    mfma_span<F, TRANS>(M, nb, r0 + c, w * kw, (w + 1) * kw, c < nc ? V + (int64_t)(c0 + c) * vsc : nullptr, vsk,
+                        lane, acc0, acc1, mul);
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[w][q + 4 * r][c] = acc0[r] + acc1[r];
     __syncthreads();
@@ -102,6 +106,7 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
         for (int x = 1; x < SW; ++x) v += red[x][rr][c];
         double* o = out + (int64_t)(c0 + c) * ldo + r0 + rr;
         *o = mode == 0 ? v : *o - v;
+        if (copy) copy[(int64_t)(r0 + rr) * nrhs + c0 + c] = v;
       }
     }
     __syncthreads();
@@ -109,76 +114,83 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
 }
 
 template <bool TRANS>
-__device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, const double* V, int64_t ldv,
-                              double* out, int64_t ldo, int nrhs, int mode, double (*red)[16][17]) {
+__device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, const double* V, int64_t vsc,
+                              int64_t vsk, double* out, int64_t ldo, int nrhs, int mode, double (*red)[16][17]) {
   switch (f) {
-    case F64: tile_mfma<F64, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
-    case F32: tile_mfma<F32, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
-    case F16: tile_mfma<F16, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
-    case BF16: tile_mfma<BF16, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red); break;
-    default: tile_mfma<F8, TRANS>(M, nb, r0, V, ldv, out, ldo, nrhs, mode, red, mul); break;
+    case F64: tile_mfma<F64, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, mode, red); break;
+    case F32: tile_mfma<F32, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, mode, red); break;
+    case F16: tile_mfma<F16, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, mode, red); break;
+    case BF16: tile_mfma<BF16, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, mode, red); break;
+    default: tile_mfma<F8, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, mode, red, mul); break;
   }
 }
 
+// Each step solves one block (diag kernel) and then updates the rest (update
+// kernel).  The diag kernel also writes the solved block by rows into stage
+// (nb x nrhs, row stride nrhs), which the update kernel reads as its
+// right-hand side: lanes then read whole rows of 16 values.
+
 // one workgroup per 16 output rows
 __global__ __launch_bounds__(STHREADS) void k_fwd_diag(int nb, const double* Linv, int k, const double* R, double* W,
-                                                  int64_t ld, int nrhs, const int* info) {
+                                                       int64_t ld, int nrhs, const int* info, double* stage) {
   if (*info) return;
   __shared__ double red[SW][16][17];
   const int64_t off = (int64_t)k * nb;
-  tile_mfma<F64, true>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, R + off, ld, W + off, ld, nrhs, 0, red);
+  tile_mfma<F64, true>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, R + off, ld, 1, W + off, ld, nrhs, 0, red, 1.0,
+                       stage);
 }
 
-__global__ __launch_bounds__(STHREADS) void k_fwd_update(TileView tv, int k, double* R, const double* W, int64_t ld,
-                                                    int nrhs) {
+__global__ __launch_bounds__(STHREADS) void k_fwd_update(TileView tv, int k, double* R, const double* stage,
+                                                         int64_t ld, int nrhs) {
   if (*tv.info) return;
   __shared__ double red[SW][16][17];
   const int nb = tv.nb, rb = nb / 16;
   const int i = k + 1 + blockIdx.x / rb;
-  tile_mfma_any<false>(tv.tile(i, k), tv.tfmt(i, k), tv.tmul(i, k), nb, (blockIdx.x % rb) * 16, W + (int64_t)k * nb, ld,
+  tile_mfma_any<false>(tv.tile(i, k), tv.tfmt(i, k), tv.tmul(i, k), nb, (blockIdx.x % rb) * 16, stage, 1, nrhs,
                        R + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
 // X_k = Linv_kk^T V_k: the stored (row-major) inverse read as column-major
 __global__ __launch_bounds__(STHREADS) void k_bwd_diag(int nb, const double* Linv, int k, const double* V, double* X,
-                                                  int64_t ld, int nrhs, const int* info) {
+                                                       int64_t ld, int nrhs, const int* info, double* stage) {
   if (*info) return;
   __shared__ double red[SW][16][17];
   const int64_t off = (int64_t)k * nb;
-  tile_mfma<F64, false>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, V + off, ld, X + off, ld, nrhs, 0, red);
+  tile_mfma<F64, false>(Linv + (int64_t)k * nb * nb, nb, blockIdx.x * 16, V + off, ld, 1, X + off, ld, nrhs, 0, red,
+                        1.0, stage);
 }
 
-__global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, double* V, const double* X, int64_t ld,
-                                                    int nrhs) {
+__global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, double* V, const double* stage,
+                                                         int64_t ld, int nrhs) {
   if (*tv.info) return;
   __shared__ double red[SW][16][17];
   const int nb = tv.nb, rb = nb / 16;
   const int i = blockIdx.x / rb;  // i < k
-  tile_mfma_any<true>(tv.tile(k, i), tv.tfmt(k, i), tv.tmul(k, i), nb, (blockIdx.x % rb) * 16, X + (int64_t)k * nb, ld,
+  tile_mfma_any<true>(tv.tile(k, i), tv.tfmt(k, i), tv.tmul(k, i), nb, (blockIdx.x % rb) * 16, stage, 1, nrhs,
                       V + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
-                           int nrhs, hipStream_t s) {
-  k_fwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info);
+                           int nrhs, double* stage, hipStream_t s) {
+  k_fwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info, stage);
   return hipGetLastError();
 }
-hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* W, int64_t ld, int nrhs,
+hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* stage, int64_t ld, int nrhs,
                              hipStream_t s) {
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
-  k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, W, ld, nrhs);
+  k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, stage, ld, nrhs);
   return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
-                           int nrhs, hipStream_t s) {
-  k_bwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info);
+                           int nrhs, double* stage, hipStream_t s) {
+  k_bwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info, stage);
   return hipGetLastError();
 }
-hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* X, int64_t ld, int nrhs,
+hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* stage, int64_t ld, int nrhs,
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, X, ld, nrhs);
+  k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, stage, ld, nrhs);
   return hipGetLastError();
 }
 
