@@ -125,6 +125,91 @@ __device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, 
   }
 }
 
+// Wide variant for the update launches with many tiles: one workgroup owns 64
+// output rows (four 16-row blocks that share each right-hand-side value it
+// loads), its four waves split the contraction into quarters.
+template <int F, bool TRANS>
+__device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t row0, int k0, int k1, const double* V,
+                                           int64_t vsk, int lane, d4 (&acc)[4], double mul) {
+  constexpr int U = 4;  // k4 steps per batch
+  const int q = lane >> 4;
+  double a[4][U], b[U], an[4][U], bn[U];
+  auto load = [&](int kk, double (*da)[U], double* db) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = kk + 4 * u + q;
+      const bool in = kk + 4 * u < k1;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int64_t row = row0 + 16 * h;
+        da[h][u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
+        if constexpr (F == F8) da[h][u] *= mul;
+      }
+      db[u] = (V && in) ? V[k * vsk] : 0.0;
+    }
+  };
+  load(k0, a, b);
+  for (int kk = k0; kk < k1; kk += 4 * U) {
+    const bool more = kk + 4 * U < k1;
+    if (more) load(kk + 4 * U, an, bn);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][u], b[u], acc[h], 0, 0, 0);
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        b[u] = bn[u];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) a[h][u] = an[h][u];
+      }
+    }
+  }
+}
+
+// out[r0 .. r0+63][c] -= sum_k op(M)[r0 + .., k] V[k][c]; V[k][c] at V[k * vsk + c * vsc];
+// the four waves' partial products are added in a fixed order
+template <int F, bool TRANS>
+__device__ void tile_mfma4(const void* M, int nb, int r0, const double* V, int64_t vsc, int64_t vsk, double* out,
+                           int64_t ldo, int nrhs, double (*red)[64][17], double mul) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int kw = nb / 4;
+  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+    const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
+    d4 acc[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) acc[h] = d4{0, 0, 0, 0};
+    mfma_span4<F, TRANS>(M, nb, r0 + c, w * kw, (w + 1) * kw, c < nc ? V + (int64_t)(c0 + c) * vsc : nullptr, vsk,
+                         lane, acc, mul);
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[w][16 * h + q + 4 * r][c] = acc[h][r];
+    __syncthreads();
+    for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
+      const int rr = e % 64, cc = e / 64;
+      if (cc < nc) {
+        const double v = ((red[0][rr][cc] + red[1][rr][cc]) + red[2][rr][cc]) + red[3][rr][cc];
+        out[(int64_t)(c0 + cc) * ldo + r0 + rr] -= v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool TRANS>
+__device__ void tile_mfma4_any(const void* M, int f, double mul, int nb, int r0, const double* V, int64_t vsc,
+                               int64_t vsk, double* out, int64_t ldo, int nrhs, double (*red)[64][17]) {
+  switch (f) {
+    case F64: tile_mfma4<F64, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, red, mul); break;
+    case F32: tile_mfma4<F32, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, red, mul); break;
+    case F16: tile_mfma4<F16, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, red, mul); break;
+    case BF16: tile_mfma4<BF16, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, red, mul); break;
+    default: tile_mfma4<F8, TRANS>(M, nb, r0, V, vsc, vsk, out, ldo, nrhs, red, mul); break;
+  }
+}
+
 // Each step solves one block (diag kernel) and then updates the rest (update
 // kernel).  The diag kernel also writes the solved block by rows into stage
 // (nb x nrhs, row stride nrhs), which the update kernel reads as its
@@ -170,6 +255,28 @@ __global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, dou
                       V + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
+__global__ __launch_bounds__(256) void k_fwd_update4(TileView tv, int k, double* R, const double* stage, int64_t ld,
+                                                     int nrhs) {
+  if (*tv.info) return;
+  __shared__ double red[4][64][17];
+  const int nb = tv.nb, rb = nb / 64;
+  const int i = k + 1 + blockIdx.x / rb;
+  tile_mfma4_any<false>(tv.tile(i, k), tv.tfmt(i, k), tv.tmul(i, k), nb, (blockIdx.x % rb) * 64, stage, 1, nrhs,
+                        R + (int64_t)i * nb, ld, nrhs, red);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_update4(TileView tv, int k, double* V, const double* stage, int64_t ld,
+                                                     int nrhs) {
+  if (*tv.info) return;
+  __shared__ double red[4][64][17];
+  const int nb = tv.nb, rb = nb / 64;
+  const int i = blockIdx.x / rb;  // i < k
+  tile_mfma4_any<true>(tv.tile(k, i), tv.tfmt(k, i), tv.tmul(k, i), nb, (blockIdx.x % rb) * 64, stage, 1, nrhs,
+                       V + (int64_t)i * nb, ld, nrhs, red);
+}
+
+constexpr int WIDE_MIN_TILES = 16;  // update launches over at least this many tiles use 64-row workgroups
+
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
                            int nrhs, double* stage, hipStream_t s) {
   k_fwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info, stage);
@@ -179,7 +286,10 @@ hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double*
                              hipStream_t s) {
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
-  k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, stage, ld, nrhs);
+  if (nt >= WIDE_MIN_TILES)
+    k_fwd_update4<<<nt * (tv.nb / 64), 256, 0, s>>>(tv, k, R, stage, ld, nrhs);
+  else
+    k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, stage, ld, nrhs);
   return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
@@ -190,7 +300,10 @@ hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double
 hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* stage, int64_t ld, int nrhs,
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, stage, ld, nrhs);
+  if (k >= WIDE_MIN_TILES)
+    k_bwd_update4<<<k * (tv.nb / 64), 256, 0, s>>>(tv, k, V, stage, ld, nrhs);
+  else
+    k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, stage, ld, nrhs);
   return hipGetLastError();
 }
 
