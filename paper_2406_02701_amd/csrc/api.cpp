@@ -103,10 +103,9 @@ struct mpcr_ctx {
   double k_ms[NKIND] = {0}, k_flops[NKIND] = {0};
   int64_t k_launches[NKIND] = {0};
   // lookahead: a second stream for the bulk of each trailing update
-  hipStream_t upd = nullptr;        // trailing updates of the factorisation, FP64 tiles
-  hipStream_t upd2 = nullptr;       // trailing updates of the factorisation, other formats
+  hipStream_t upd = nullptr;        // trailing updates of the factorisation
   hipStream_t col = nullptr;        // updates of the next panel column
-  std::vector<hipEvent_t> sync_ev;  // timing-disabled events, 4 per step
+  std::vector<hipEvent_t> sync_ev;  // timing-disabled events, 3 per step
 };
 
 namespace {
@@ -148,7 +147,7 @@ hipError_t timed(mpcr_ctx* ctx, hipStream_t s, int kind, double flops, F&& launc
 }
 
 hipError_t ensure_lookahead(mpcr_ctx* ctx, size_t nev) {
-  for (hipStream_t* st : {&ctx->upd, &ctx->upd2, &ctx->col})
+  for (hipStream_t* st : {&ctx->upd, &ctx->col})
     if (!*st) {
       hipError_t e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
       if (e != hipSuccess) return e;
@@ -386,39 +385,33 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
 }
 
 // Queues the right-looking factorisation of an already filled tile store with
-// a depth-1 lookahead over four streams.  The context's stream P carries the
+// a depth-1 lookahead over three streams.  The context's stream P carries the
 // critical path: POTRF(k), TRSM(k), then the SYRK of the next diagonal tile
 // (k+1, k+1), so POTRF(k+1) can start at once.  Stream C updates the rest of
 // column k+1 (the next panel) from panel k while POTRF(k+1) runs; P waits for
-// it before TRSM(k+1).  The rest of step k's trailing update (columns k+2 ..)
-// runs on U for the FP64 tiles and on U2 for the others, so that the two
-// formats' launches overlap; each stream's steps stay in order, and every
-// tile is updated by one of them only.  U, U2 and C wait for TRSM(k); P and C
-// wait for both update streams' step k-1 before they touch column k+1, which
-// that step also updates.
+// it before TRSM(k+1).  Stream U carries the rest of step k's trailing update
+// (columns k+2 ..).  U and C wait for TRSM(k); P and C wait for U's step k-1
+// before they touch column k+1, which that step also updates.
 int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   hipStream_t P = ctx->stream;
   TileView tv = f->view();
   f->linv_ready = false;
   const double nb3 = (double)f->nb * f->nb * f->nb;
   const int64_t nt = f->nt;
-  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(4 * nt + 2)));
-  hipStream_t U = ctx->upd, U2 = ctx->upd2, C = ctx->col;
+  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(3 * nt + 2)));
+  hipStream_t U = ctx->upd, C = ctx->col;
   auto ev = [&](int64_t i) { return ctx->sync_ev[i]; };      // 2k: TRSM(k) done (P), 2k+1: U's step k done
   auto evc = [&](int64_t k) { return ctx->sync_ev[2 * nt + 2 + k]; };  // C's column k+1 done
-  auto ev2 = [&](int64_t k) { return ctx->sync_ev[3 * nt + 2 + k]; };  // U2's step k done
-  // U, U2 and C start after everything queued on P so far (the tile fill)
+  // U and C start after everything queued on P so far (the tile fill)
   HIP_TRY(ctx, hipEventRecord(ev(2 * nt), P));
   HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * nt), 0));
-  HIP_TRY(ctx, hipStreamWaitEvent(U2, ev(2 * nt), 0));
   HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * nt), 0));
   static const int order[5] = {F64, F32, BF16, F16, F8};
   const int64_t nb2 = f->nb * f->nb;
   // which: 0 = the SYRK of the next diagonal tile, 1 = the rest of the next
   // column, 2 = the columns after it
-  auto launch_updates = [&](int64_t k, hipStream_t s0, int which) -> int {
+  auto launch_updates = [&](int64_t k, hipStream_t s, int which) -> int {
     for (int p : order) {
-      hipStream_t s = (which == 2 && p != F64) ? U2 : s0;
       const int all = f->task_cnt[k * 5 + p], nx = f->task_cnt_next[k * 5 + p];
       // the next column's tasks come first, its diagonal tile (FP64) first among them
       const int nd = (p == F64 && nx > 0) ? 1 : 0;
@@ -454,26 +447,17 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
     if (f->task_cnt[k * 5 + F8] > 0)  // operand scales of the FP8 updates (buffer of this step's parity)
       HIP_TRY(ctx, launch_panel_amax(tv, (int)k, f->d_pamax + (k & 1) * nt, P));
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
-    if (k > 0) {  // U and U2 finished step k-1
-      HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));
-      HIP_TRY(ctx, hipStreamWaitEvent(P, ev2(k - 1), 0));
-    }
+    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
     if ((rc = launch_updates(k, P, 0)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * k), 0));
-    if (k > 0) {
-      HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * (k - 1) + 1), 0));
-      HIP_TRY(ctx, hipStreamWaitEvent(C, ev2(k - 1), 0));
-    }
+    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * (k - 1) + 1), 0));
     if ((rc = launch_updates(k, C, 1)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipEventRecord(evc(k), C));
     HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * k), 0));
-    HIP_TRY(ctx, hipStreamWaitEvent(U2, ev(2 * k), 0));
     if ((rc = launch_updates(k, U, 2)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipEventRecord(ev(2 * k + 1), U));
-    HIP_TRY(ctx, hipEventRecord(ev2(k), U2));
   }
   HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * nt - 1), 0));  // join
-  HIP_TRY(ctx, hipStreamWaitEvent(P, ev2(nt - 1), 0));
   HIP_TRY(ctx, hipStreamWaitEvent(P, evc(nt - 1), 0));
   return MPCR_OK;
 }
@@ -826,7 +810,6 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     for (auto& e : ctx->sync_ev) (void)hipEventDestroy(e);
     if (ctx->upd) (void)hipStreamDestroy(ctx->upd);
     if (ctx->col) (void)hipStreamDestroy(ctx->col);
-    if (ctx->upd2) (void)hipStreamDestroy(ctx->upd2);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
