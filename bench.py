@@ -356,10 +356,10 @@ def main():
 
     dom = max(range(NKIND), key=lambda k: kstats[k][0])
     roofline = roof(kstats, dom, measured_traffic(KIND_NAME[dom]))
-    # the factorisation runs its trailing updates on two streams by format plus
-    # the critical-path streams, so a launch's duration includes the kernels it
-    # shares the GPU with; the FP64 path has no FP32 launches beside its FP64 ones
-    roofline["overlap"] = "launches share the GPU with the other update stream and the POTRF/TRSM stream"
+    # the trailing updates share the GPU with the next-column and POTRF/TRSM
+    # streams, so a launch's duration includes some sharing; the FP64 path's
+    # figure is given beside it
+    roofline["overlap"] = "launches share the GPU with the next-column update and POTRF/TRSM streams"
     roofline_fp64_path = roof(kstats64, 0, None)
 
     fl_by = list(d_mix.flops_by_prec)
