@@ -146,9 +146,9 @@ hipError_t timed(mpcr_ctx* ctx, hipStream_t s, int kind, double flops, F&& launc
   return e;
 }
 
-hipError_t ensure_lookahead(mpcr_ctx* ctx, size_t nev) {
+hipError_t ensure_lookahead(mpcr_ctx* ctx, size_t nev, bool need_col) {
   for (hipStream_t* st : {&ctx->upd, &ctx->col})
-    if (!*st) {
+    if (!*st && (st != &ctx->col || need_col)) {
       hipError_t e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
       if (e != hipSuccess) return e;
     }
@@ -392,14 +392,20 @@ int make_factor(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>
 // it before TRSM(k+1).  Stream U carries the rest of step k's trailing update
 // (columns k+2 ..).  U and C wait for TRSM(k); P and C wait for U's step k-1
 // before they touch column k+1, which that step also updates.
+constexpr int64_t COL_STREAM_MIN_NT = 32;  // more tiles per dimension than this: next column on its own stream
+
 int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   hipStream_t P = ctx->stream;
   TileView tv = f->view();
   f->linv_ready = false;
   const double nb3 = (double)f->nb * f->nb * f->nb;
   const int64_t nt = f->nt;
-  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(3 * nt + 2)));
-  hipStream_t U = ctx->upd, C = ctx->col;
+  // the column stream pays off once the trailing updates are long enough to
+  // hide POTRF(k+1) behind; small factorisations (serving) keep the next
+  // column on P, which then runs POTRF(k), TRSM(k) and the whole column k+1
+  const bool use_col = nt > COL_STREAM_MIN_NT;
+  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(3 * nt + 2), use_col));
+  hipStream_t U = ctx->upd, C = use_col ? ctx->col : P;
   auto ev = [&](int64_t i) { return ctx->sync_ev[i]; };      // 2k: TRSM(k) done (P), 2k+1: U's step k done
   auto evc = [&](int64_t k) { return ctx->sync_ev[2 * nt + 2 + k]; };  // C's column k+1 done
   // U and C start after everything queued on P so far (the tile fill)
