@@ -37,8 +37,45 @@ __device__ __forceinline__ void tri_unpack(int t, int& i, int& j) {
   j = t - ii * (ii + 1) / 2;
 }
 
-// One workgroup per (lower tile, 16-column slab); threads walk rows so that
-// stores into the column-major tile are contiguous.
+// One workgroup per (lower tile, 16-column slab); each thread owns rows r of
+// the tile (consecutive across threads, so stores are coalesced) and walks the
+// 16 columns; a column's coordinates are the same for the whole workgroup.
+// The tile's format is resolved once per workgroup.
+template <int MODE, int F>
+__device__ __forceinline__ void fill_slab(void* tile, int sc, int ti, int tj, int c0, int nb, int n,
+                                          const double* src, int64_t lds, double s2, double range, int nuc,
+                                          double nugget, double* sig) {
+  for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+    const int R = ti * nb + r;
+    const bool rin = R < n;
+    double xr = 0.0, yr = 0.0;
+    if (MODE == 0 && rin) {
+      xr = src[R];
+      yr = src[n + R];
+    }
+#pragma unroll 4
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = c0 + cc, C = tj * nb + c;
+      double v;
+      if (!rin || C >= n) {
+        v = (R == C) ? 1.0 : 0.0;
+      } else if (MODE == 0) {
+        const double dx = xr - src[C];
+        const double dy = yr - src[n + C];
+        const double d = sqrt(dx * dx + dy * dy);
+        v = s2 * matern_corr(d / range, nuc);
+        if (R == C) v += nugget;
+      } else {
+        const int hi = R > C ? R : C, lo = R > C ? C : R;
+        v = src[(int64_t)lo * lds + hi];
+      }
+      const int64_t idx = (int64_t)c * nb + r;
+      store_round(tile, F, idx, F == F8 ? ldexp(v, sc) : v);
+      if (sig) sig[idx] = v;
+    }
+  }
+}
+
 template <int MODE>  // 0: from covariance, 1: from dense FP64 lower triangle
 __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* src, int64_t lds, double s2,
                                                    double range, int nuc, double nugget, double* sig64) {
@@ -49,20 +86,13 @@ __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* s
   const int f = tv.tfmt(ti, tj);
   const int sc = f == F8 ? tv.tscale(ti, tj) : 0;  // FP8 tiles hold codes of v 2^sc
   const int c0 = blockIdx.y * 16;
-  for (int e = threadIdx.x; e < 16 * nb; e += blockDim.x) {
-    int c = c0 + e / nb, r = e % nb;
-    int R = ti * nb + r, C = tj * nb + c;
-    double v;
-    if (R >= n || C >= n) {
-      v = (R == C) ? 1.0 : 0.0;
-    } else if (MODE == 0) {
-      v = cov_entry(src, n, R, C, s2, range, nuc, nugget);
-    } else {
-      int hi = R > C ? R : C, lo = R > C ? C : R;
-      v = src[(int64_t)lo * lds + hi];
-    }
-    store_round(tile, f, (int64_t)c * nb + r, f == F8 ? ldexp(v, sc) : v);
-    if (sig64) sig64[(int64_t)blockIdx.x * nb * nb + (int64_t)c * nb + r] = v;  // FP64 copy, packed tile order
+  double* sig = sig64 ? sig64 + (int64_t)blockIdx.x * nb * nb : nullptr;  // FP64 copy, packed tile order
+  switch (f) {
+    case F64: fill_slab<MODE, F64>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
+    case F32: fill_slab<MODE, F32>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
+    case F16: fill_slab<MODE, F16>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
+    case BF16: fill_slab<MODE, BF16>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
+    default: fill_slab<MODE, F8>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
   }
 }
 
