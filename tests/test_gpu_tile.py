@@ -141,6 +141,26 @@ def test_fp64_factor_kms_closed_form(g, n, nb):
     mpcr.mpcr_factor_destroy(f)
 
 
+@pytest.mark.parametrize("n,nb,nu,rng,nug", [(2048, 512, 2.5, 0.2, 1e-10), (2048, 256, 1.5, 0.3, 1e-12)])
+def test_fp64_factor_ill_conditioned_backward_error(g, n, nb, nu, rng, nug):
+    """The triangular solves inside the factorisation multiply by inverted
+    32 x 32 diagonal blocks; on covariances with tiny nuggets (condition
+    numbers far beyond 1e10) the factor's backward error must still be at the
+    rounding level of a Cholesky factorisation, and it must match the oracle's
+    factor to its conditioning."""
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    locs = synth.locations(n, 11)
+    locs = locs[cov.morton_order(locs)]
+    S = np.asfortranarray(cov.covariance(locs, 1.0, rng, nu, nug))
+    f, _ = _factor_dense(gu, ctx, S, nb, tiled.tilemap_uniform(n, nb))
+    L = _to_dense(gu, ctx, f, n)
+    Ld = dense.cholesky_lower(S)
+    assert np.linalg.norm(L @ L.T - S) / np.linalg.norm(S) <= 4 * n * 2.0 ** -53
+    assert np.linalg.norm(L - Ld) / np.linalg.norm(Ld) <= 4 * n * 2.0 ** -53 * np.linalg.cond(Ld)
+    mpcr.mpcr_factor_destroy(f)
+
+
 @pytest.mark.parametrize("n,nb,nu", [(1000, 128, 1.5), (777, 256, 0.5), (1536, 512, 2.5)])
 def test_fp64_factor_matches_oracle(g, n, nb, nu):
     gu, ctx = g
