@@ -748,25 +748,48 @@ __device__ __forceinline__ void trsm_rows16_inv(const double* X, const double* L
                                                 int c0, int c1, int r0, double (*Ts)[PW + 1], int lane, LoadA load_a,
                                                 StoreX store_x) {
   const int q = lane >> 4, c = lane & 15;
+  // A and D_J^{-1} of the next chunk are requested before the current chunk's
+  // product, so their latency hides behind it
+  double av[8], dv[PW / 2];
+  auto fetch = [&](int J0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = q + 4 * r;
+      av[2 * r] = load_a((int64_t)(J0 + c) * ld + r0 + R);
+      av[2 * r + 1] = load_a((int64_t)(J0 + c + 16) * ld + r0 + R);
+    }
+    const double* Di = dinv + (int64_t)(J0 / PW) * PW * PW;  // Di[kk * 32 + n] = D_J^{-1}[n][kk]
+#pragma unroll
+    for (int u = 0; u < PW / 4; ++u) {
+      dv[2 * u] = Di[(4 * u + q) * PW + c];
+      dv[2 * u + 1] = Di[(4 * u + q) * PW + 16 + c];
+    }
+  };
+  fetch(c0);
 #pragma unroll 1
   for (int J0 = c0; J0 < c1; J0 += PW) {
+    double ca[8], cd[PW / 2];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ca[e] = av[e];
+#pragma unroll
+    for (int e = 0; e < PW / 2; ++e) cd[e] = dv[e];
+    if (J0 + PW < c1) fetch(J0 + PW);
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     mfma_rows16x32(X, L, ld, r0, J0, c0, J0, lane, acc0, acc1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int R = q + 4 * r;
-      Ts[R][c] = load_a((int64_t)(J0 + c) * ld + r0 + R) - acc0[r];
-      Ts[R][c + 16] = load_a((int64_t)(J0 + c + 16) * ld + r0 + R) - acc1[r];
+      Ts[R][c] = ca[2 * r] - acc0[r];
+      Ts[R][c + 16] = ca[2 * r + 1] - acc1[r];
     }
     __builtin_amdgcn_wave_barrier();
-    const double* Di = dinv + (int64_t)(J0 / PW) * PW * PW;  // Di[kk * 32 + n] = D_J^{-1}[n][kk]
     d4 x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
 #pragma unroll
     for (int u = 0; u < PW / 4; ++u) {
       const int kk = 4 * u + q;
       const double a = Ts[c][kk];
-      x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Di[kk * PW + c], x0, 0, 0, 0);
-      x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Di[kk * PW + 16 + c], x1, 0, 0, 0);
+      x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cd[2 * u], x0, 0, 0, 0);
+      x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cd[2 * u + 1], x1, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
