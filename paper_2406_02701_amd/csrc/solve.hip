@@ -38,6 +38,7 @@ __device__ __forceinline__ double ldw(const void* p, int64_t i) {
 constexpr int MB = 8;  // k4 steps per batch
 constexpr int SW = 8;  // waves per workgroup of the tile products (each nb / SW of the contraction)
 constexpr int STHREADS = 64 * SW;
+constexpr int SW4 = 8;  // waves per workgroup of the wide update products
 
 // acc0/acc1 += op(M)[row, k0 .. k1) * V[k0 .. k1, c], op(M)[row][k] = M[k * ldm + row]
 // (TRANS false) or M[row * ldm + k] (TRANS true); V is this lane's column of
@@ -127,7 +128,7 @@ __device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, 
 
 // Wide variant for the update launches with many tiles: one workgroup owns 64
 // output rows (four 16-row blocks that share each right-hand-side value it
-// loads), its four waves split the contraction into quarters.
+// loads), its SW4 waves split the contraction into equal parts.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t row0, int k0, int k1, const double* V,
                                            int64_t vsk, int lane, d4 (&acc)[4], double mul) {
@@ -168,13 +169,13 @@ __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t r
 }
 
 // out[r0 .. r0+63][c] -= sum_k op(M)[r0 + .., k] V[k][c]; V[k][c] at V[k * vsk + c * vsc];
-// the four waves' partial products are added in a fixed order
+// the waves' partial products are added in a fixed order
 template <int F, bool TRANS>
 __device__ void tile_mfma4(const void* M, int nb, int r0, const double* V, int64_t vsc, int64_t vsk, double* out,
                            int64_t ldo, int nrhs, double (*red)[64][17], double mul) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int q = lane >> 4, c = lane & 15;
-  const int kw = nb / 4;
+  const int kw = nb / SW4;
   for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     d4 acc[4];
@@ -187,10 +188,12 @@ __device__ void tile_mfma4(const void* M, int nb, int r0, const double* V, int64
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[w][16 * h + q + 4 * r][c] = acc[h][r];
     __syncthreads();
-    for (int e = tid; e < 64 * RHS_CHUNK; e += 256) {
+    for (int e = tid; e < 64 * RHS_CHUNK; e += 64 * SW4) {
       const int rr = e % 64, cc = e / 64;
       if (cc < nc) {
-        const double v = ((red[0][rr][cc] + red[1][rr][cc]) + red[2][rr][cc]) + red[3][rr][cc];
+        double v = red[0][rr][cc];
+#pragma unroll
+        for (int x = 1; x < SW4; ++x) v += red[x][rr][cc];
         out[(int64_t)(c0 + cc) * ldo + r0 + rr] -= v;
       }
     }
@@ -255,20 +258,20 @@ __global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, dou
                       V + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
-__global__ __launch_bounds__(256) void k_fwd_update4(TileView tv, int k, double* R, const double* stage, int64_t ld,
+__global__ __launch_bounds__(64 * SW4) void k_fwd_update4(TileView tv, int k, double* R, const double* stage, int64_t ld,
                                                      int nrhs) {
   if (*tv.info) return;
-  __shared__ double red[4][64][17];
+  __shared__ double red[SW4][64][17];
   const int nb = tv.nb, rb = nb / 64;
   const int i = k + 1 + blockIdx.x / rb;
   tile_mfma4_any<false>(tv.tile(i, k), tv.tfmt(i, k), tv.tmul(i, k), nb, (blockIdx.x % rb) * 64, stage, 1, nrhs,
                         R + (int64_t)i * nb, ld, nrhs, red);
 }
 
-__global__ __launch_bounds__(256) void k_bwd_update4(TileView tv, int k, double* V, const double* stage, int64_t ld,
+__global__ __launch_bounds__(64 * SW4) void k_bwd_update4(TileView tv, int k, double* V, const double* stage, int64_t ld,
                                                      int nrhs) {
   if (*tv.info) return;
-  __shared__ double red[4][64][17];
+  __shared__ double red[SW4][64][17];
   const int nb = tv.nb, rb = nb / 64;
   const int i = blockIdx.x / rb;  // i < k
   tile_mfma4_any<true>(tv.tile(k, i), tv.tfmt(k, i), tv.tmul(k, i), nb, (blockIdx.x % rb) * 64, stage, 1, nrhs,
@@ -287,7 +290,7 @@ hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double*
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
   if (nt >= WIDE_MIN_TILES)
-    k_fwd_update4<<<nt * (tv.nb / 64), 256, 0, s>>>(tv, k, R, stage, ld, nrhs);
+    k_fwd_update4<<<nt * (tv.nb / 64), 64 * SW4, 0, s>>>(tv, k, R, stage, ld, nrhs);
   else
     k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, stage, ld, nrhs);
   return hipGetLastError();
@@ -301,7 +304,7 @@ hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double*
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (k >= WIDE_MIN_TILES)
-    k_bwd_update4<<<k * (tv.nb / 64), 256, 0, s>>>(tv, k, V, stage, ld, nrhs);
+    k_bwd_update4<<<k * (tv.nb / 64), 64 * SW4, 0, s>>>(tv, k, V, stage, ld, nrhs);
   else
     k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, stage, ld, nrhs);
   return hipGetLastError();
