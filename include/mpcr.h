@@ -102,13 +102,32 @@ typedef struct {
  *   residual     mpcr_gauss_loglik only: 0 = regenerate Sigma's entries from the
  *                sites for every residual (no extra memory); 1 = keep an FP64
  *                copy of Sigma's lower tiles (nt(nt+1)/2 nb^2 doubles, written
- *                with the low-precision tiles) and stream it */
+ *                with the low-precision tiles) and stream it
+ *   promote_on_breakdown
+ *                mpcr_gauss_loglik only: 1 = when the mixed factor meets a
+ *                non-positive pivot (global column info, tile step
+ *                k = (info-1)/nb), take the coarsest format p among the tiles
+ *                (i, j), j < i <= k, and the smallest distance d_fail = i - j at
+ *                which p occurs there; move every tile of format p with
+ *                distance >= d_fail one format up (FP8 -> FP16, FP16/BF16 ->
+ *                FP32, FP32 -> FP64) and factor again, at most 8 times, until
+ *                the factor exists or the leading tiles are all FP64.  The map
+ *                finally used is returned by mpcr_loglik_map and the number of
+ *                promotions in mpcr_diag_t.promotions.  (The paper's MLE
+ *                section warns that low precision can fail on ill-conditioned
+ *                covariances; this is the recovery.)  0 = report NOT_SPD.
+ *   direct_eta   all-FP64 map with max_iter = 0 (the paper's direct path):
+ *                1 = also compute the backward error of the direct solve (one
+ *                extra FP64 residual pass) into diag->eta / rel_resid2;
+ *                0 = skip it.  opts == NULL behaves as 1 when diag != NULL. */
 typedef struct {
   double tol;
   int max_iter;
   int solver;
   int recompute;
   int residual;
+  int promote_on_breakdown;
+  int direct_eta;
 } mpcr_refine_opts_t;
 
 /* Diagnostics filled by mpcr_potrs / mpcr_gauss_loglik (host struct). */
@@ -122,6 +141,7 @@ typedef struct {
   int64_t info;           /* LAPACK-style info of the factorisation */
   double t_gen_ms, t_factor_ms, t_solve_ms, t_refine_ms;  /* phase times (HIP events) */
   double flops_by_prec[5];  /* algorithmic factorisation flops by compute format */
+  int promotions;         /* refactorisations after a breakdown (promote_on_breakdown) */
 } mpcr_diag_t;
 
 /* ---- context -------------------------------------------------------------- */
@@ -206,7 +226,8 @@ int mpcr_covariance_tile_amax(mpcr_ctx* ctx, int64_t n, int64_t nb, const double
  * *out receives a factor that owns its device tiles; *h_info receives 0 or
  * the 1-based global column of the first non-positive pivot, in which case the
  * call returns MPCR_ERR_NOT_SPD and *out is still valid (destroy it).
- * FP8 tiles are not accepted here (MPCR_ERR_ARG). */
+ * FP8-E4M3 tiles carry one power-of-two scale each, chosen from the tile's
+ * largest magnitude whenever the tile receives new values (A9's rule). */
 int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda,
                      const mpcr_tilemap_t* map, mpcr_factor** out, int64_t* h_info);
 
@@ -250,16 +271,45 @@ int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* f, int64_t nrhs, const double* 
  *   l = -(n/2) log(2 pi) - (1/2) log|Sigma| - (1/2) z^T Sigma^{-1} z.
  * Sites are taken in Morton order when `order` is 1 (l is invariant under a
  * joint permutation of sites and observations).  map == NULL means all tiles
- * FP64 with tile size nb_default (=256).  With an all-FP64 map and opts NULL
- * the quadratic form is ||L^{-1} z||^2 (the paper's forwardsolve + SquareSum);
- * otherwise the solve is refined in FP64 with the residual computed
- * matrix-free from the sites, and quad = z^T x + x^T r.
+ * FP64 with tile size nb_default (=256).  With an all-FP64 map and either
+ * opts NULL or opts->max_iter = 0 the quadratic form is ||L^{-1} z||^2 (the
+ * paper's forwardsolve + SquareSum); otherwise the solve is refined in FP64
+ * (residual from the sites or from stored FP64 tiles, opts->residual) and
+ * quad = z^T x + x^T r.  A mixed map with opts->max_iter = 0 takes
+ * x = M^{-1} z with its true residual r.
  * h_loglik (host, nrhs doubles) receives l per column; diag may be NULL.
  * The covariance tiles and factor live in a workspace owned by ctx. */
 int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_Z,
                       int64_t nrhs, const mpcr_theta_t* theta, const mpcr_tilemap_t* map,
                       int order, const mpcr_refine_opts_t* opts, double* h_loglik,
                       mpcr_diag_t* diag);
+
+/* The tile map used by the context's last mpcr_gauss_loglik call (after any
+ * promotions): *h_nt receives nt, and h_map_out (host, capacity bytes) the
+ * nt*nt map when capacity >= nt*nt.  Errors: MPCR_ERR_ARG (no call yet, or
+ * capacity too small; *h_nt is still set). */
+int mpcr_loglik_map(const mpcr_ctx* ctx, int64_t* h_nt, uint8_t* h_map_out, int64_t capacity);
+
+/* Maximum likelihood fit of the Matern range and variance (the paper's MLE
+ * section: R's optim, Nelder-Mead, minimises the negative log-likelihood with
+ * nu fixed and the parameters on the log scale).  p = (log range, log
+ * variance); f(p) = -l(theta(p)) evaluated by mpcr_gauss_loglik on the sites
+ * d_locs (n x 2, column-major) and one observation vector d_z (n), with the
+ * tile map `map` (NULL: all FP64, nb 256) and refinement options `refine`
+ * (may be NULL); a breakdown of the factor counts as f = +inf.  The sites are
+ * put in Morton order once; every evaluation reuses the context's factor
+ * workspace.  The simplex method: Nelder and Mead (1965) as stated by
+ * Lagarias et al. (1998) with reflection 1, expansion 2, contraction 1/2 and
+ * shrink 1/2, vertices ordered by f with ties kept in place; first simplex
+ * h_x0 and h_x0 + s e_i with s = 0.1 max|x0_i| (0.1 if x0 = 0); stop when
+ * f_worst - f_best <= reltol (|f_best| + reltol) or after max_iter
+ * iterations.  Outputs (host): h_x_out[2] the best vertex, *h_nll_out its f,
+ * *h_iters / *h_evals (may be NULL) iterations and likelihood evaluations.
+ * Errors: MPCR_ERR_ARG; any error of mpcr_gauss_loglik other than NOT_SPD
+ * ends the fit with that code. */
+int mpcr_mle_fit(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_z, double nu, double nugget,
+                 const mpcr_tilemap_t* map, const mpcr_refine_opts_t* refine, const double* h_x0, int max_iter,
+                 double reltol, double* h_x_out, double* h_nll_out, int* h_iters, int* h_evals);
 
 /* ---- matrix product ----------------------------------------------------------- */
 
@@ -295,7 +345,10 @@ int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m
  * from the arena (no hipMalloc / hipFree per request).  Each request is one
  * mpcr_gauss_loglik evaluation (sites in Morton order, one observation
  * vector) with the norm-guarded banded map below; a request whose mixed
- * factor breaks down is recomputed with all tiles FP64 (fallback).  A
+ * factor breaks down is refactored with promoted tiles when
+ * refine.promote_on_breakdown is 1, and recomputed with all tiles FP64 when
+ * it still fails and fallback_fp64 is 1.  refine.residual must be 0 (the
+ * footprint estimate assumes the matrix-free residual).  A
  * request's arithmetic does not depend on what else is running: results are
  * the same alone and in a mix. */
 typedef struct mpcr_server mpcr_server;
@@ -310,7 +363,8 @@ typedef struct {
   int fallback_fp64;       /* 1: recompute with an all-FP64 map on breakdown */
 } mpcr_serve_opts_t;
 
-/* Errors: MPCR_ERR_ARG, MPCR_ERR_NOMEM (budget cannot be allocated). */
+/* Errors: MPCR_ERR_ARG (bad options, refine.residual != 0), MPCR_ERR_NOMEM
+ * (budget cannot be allocated). */
 int mpcr_serve_create(int device, size_t hbm_budget, int max_slots, const mpcr_serve_opts_t* opts,
                       mpcr_server** out);
 /* Waits for the requests in flight, drops queued ones, frees everything. */

@@ -121,14 +121,3 @@ def gemm(A: np.ndarray, B: np.ndarray, transA=False, transB=False, alpha=1.0, be
     if C is not None and beta != 0.0:
         out = out + beta * np.asarray(C, np.float64)
     return out
-
-
-def backward_error(Sigma_matvec, B, X, sigma_inf_norm):
-    """Normwise backward error per column,
-        eta = ||b - Sigma x||_inf / (||Sigma||_inf ||x||_inf + ||b||_inf),
-    and the 2-norm relative residual ||b - Sigma x||_2 / ||b||_2.  Returns the
-    maxima over columns."""
-    R = B - Sigma_matvec(X)
-    eta = np.max(np.abs(R), axis=0) / (sigma_inf_norm * np.max(np.abs(X), axis=0) + np.max(np.abs(B), axis=0))
-    rel = np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
-    return float(np.max(eta)), float(np.max(rel))

@@ -20,7 +20,7 @@ from . import covariance as cov
 from .dense import (NotPositiveDefinite, backward_substitution_transpose, forward_substitution,
                     gaussian_loglik, logdet_from_cholesky, loglik_fp64)
 from .refine import iterative_refinement, pcg, quad_refined
-from .tiled import tile_cholesky_emulated
+from .tiled import promote_after_breakdown, tile_cholesky_emulated
 
 
 def order_sites(locs, Z):
@@ -33,14 +33,26 @@ def loglik_plain(locs, Z, sigma2, range_, nu, nugget):
     return loglik_fp64(S, Z)
 
 
-def loglik_mixed(locs, Z, sigma2, range_, nu, nugget, nb, tmap, tol=1e-9, max_iter=200, solver="pcg"):
+def loglik_mixed(locs, Z, sigma2, range_, nu, nugget, nb, tmap, tol=1e-9, max_iter=200, solver="pcg",
+                 promote=False):
+    """With ``promote``, a breakdown is followed by a refactorisation with the
+    map of ``promote_after_breakdown`` until the factor exists or nothing is
+    left to promote; the map used and the number of promotions are returned."""
     Z = np.asarray(Z, dtype=np.float64)
     Z2 = Z[:, None] if Z.ndim == 1 else Z
     n = locs.shape[0]
     S = cov.covariance(locs, sigma2, range_, nu, nugget)
-    fac = tile_cholesky_emulated(S, nb, tmap)
+    promotions = 0
+    while True:
+        fac = tile_cholesky_emulated(S, nb, tmap)
+        if not (fac["info"] and promote):
+            break
+        nxt = promote_after_breakdown(tmap, nb, fac["info"])
+        if np.array_equal(nxt, tmap):
+            break
+        tmap, promotions = nxt, promotions + 1
     if fac["info"]:
-        return dict(info=fac["info"], L=fac["L"])
+        return dict(info=fac["info"], L=fac["L"], map=tmap, promotions=promotions)
     L = fac["L"][:n, :n]
     logdet = logdet_from_cholesky(L)
     sig_inf = float(np.max(np.sum(np.abs(S), axis=1)))
@@ -52,4 +64,4 @@ def loglik_mixed(locs, Z, sigma2, range_, nu, nugget, nb, tmap, tol=1e-9, max_it
     rel = np.linalg.norm(res["R"], axis=0) / np.linalg.norm(Z2, axis=0)
     return dict(info=0, L=L, logdet=logdet, quad=quad, loglik=gaussian_loglik(n, logdet, quad),
                 X=res["X"], iters=res["iters"], eta=res["eta"], converged=res["converged"],
-                rel_resid2=float(np.max(rel)))
+                rel_resid2=float(np.max(rel)), map=tmap, promotions=promotions)

@@ -139,3 +139,80 @@ def tile_cholesky_emulated(Sigma: np.ndarray, nb: int, tmap: np.ndarray):
                 upd = round_tile(A[T(i, k)], f) @ round_tile(Ljk, f).T
                 A[T(i, j)] = round_tile(A[T(i, j)] - upd, f)
     return dict(L=np.tril(A), info=0, N=N)
+
+
+# ---------------------------------------------------------------------------
+# Norm-guarded tile map and promotion after a breakdown (readings of the
+# Discussion section's tiled multi-precision method together with the MLE
+# section's warning that low precision fails on ill-conditioned covariances).
+# ---------------------------------------------------------------------------
+
+# Each format's next finer format when a tile has to be promoted.
+PROMOTE_TO = {CODE["fp8_e4m3"]: CODE["fp16"], CODE["fp16"]: CODE["fp32"], CODE["bf16"]: CODE["fp32"],
+              CODE["fp32"]: FP64_CODE, FP64_CODE: FP64_CODE}
+
+
+def tile_amax(Sigma: np.ndarray, nb: int) -> np.ndarray:
+    """nt x nt array: the largest |Sigma_ij| of every lower tile (i >= j, the
+    last tile row/column cut at n); 0 above the diagonal."""
+    n = Sigma.shape[0]
+    nt = num_tiles(n, nb)
+    out = np.zeros((nt, nt))
+    for i in range(nt):
+        for j in range(i + 1):
+            out[i, j] = np.max(np.abs(Sigma[i * nb:min((i + 1) * nb, n), j * nb:min((j + 1) * nb, n)]))
+    return out
+
+
+def rounding_bound(code: int, amax: float) -> float:
+    """Largest absolute error of rounding values of magnitude <= amax to the
+    format: max(u amax, half the smallest subnormal).  An FP8 tile carries its
+    own power-of-two scale, so only the relative term applies to it."""
+    f = fmt_of(int(code))
+    if f.name == "fp64":
+        return f.unit_roundoff * amax
+    rel = f.unit_roundoff * amax
+    if f.name == "fp8_e4m3":
+        return rel
+    return max(rel, 2.0 ** (f.emin - f.mbits - 1))
+
+
+def tilemap_guarded(banded: np.ndarray, amax: np.ndarray, guard: float) -> np.ndarray:
+    """Each off-diagonal tile keeps its banded format p if rounding_bound(p,
+    max|tile|) <= guard; otherwise it climbs PROMOTE_TO until the bound holds
+    (FP64 always does)."""
+    nt = banded.shape[0]
+    out = np.full((nt, nt), UNUSED, dtype=np.uint8)
+    for i in range(nt):
+        for j in range(i + 1):
+            p = int(banded[i, j])
+            while p != FP64_CODE and rounding_bound(p, float(amax[i, j])) > guard:
+                p = PROMOTE_TO[p]
+            out[i, j] = p
+    return out
+
+
+def promote_after_breakdown(tmap: np.ndarray, nb: int, info: int) -> np.ndarray:
+    """The map to refactor with after a breakdown at global column `info`
+    (1-based).  The pivot of tile step k = (info-1)//nb depends on the leading
+    (k+1) x (k+1) tiles; let p be the coarsest format among them and d_fail
+    the smallest tile distance i - j at which p occurs there.  Every tile of
+    the whole map with format p and distance >= d_fail moves one format up
+    (PROMOTE_TO).  Returns the map unchanged when the leading block is all
+    FP64 (nothing left to promote)."""
+    nt = tmap.shape[0]
+    k = (int(info) - 1) // nb
+    rank = {CODE["fp8_e4m3"]: 0, CODE["fp16"]: 1, CODE["bf16"]: 1, CODE["fp32"]: 2, FP64_CODE: 3}
+    lead = [(i, j, int(tmap[i, j])) for i in range(k + 1) for j in range(i)]
+    low = [t for t in lead if t[2] != FP64_CODE]
+    out = tmap.copy()
+    if not low:
+        return out
+    r = min(rank[p] for _, _, p in low)
+    coarse = {p for _, _, p in low if rank[p] == r}
+    d_fail = min(i - j for i, j, p in low if p in coarse)
+    for i in range(nt):
+        for j in range(i):
+            if int(tmap[i, j]) in coarse and i - j >= d_fail:
+                out[i, j] = PROMOTE_TO[int(tmap[i, j])]
+    return out

@@ -277,8 +277,7 @@ void free_factor(mpcr_factor* f) {
 bool valid_prec(int p) { return p >= 0 && p <= 4; }
 
 // Checks a tile map and copies it (nt x nt) into out.
-int check_map(mpcr_ctx* ctx, int64_t n, const mpcr_tilemap_t* map, std::vector<uint8_t>& out, int64_t& nb,
-              bool allow_fp8) {
+int check_map(mpcr_ctx* ctx, int64_t n, const mpcr_tilemap_t* map, std::vector<uint8_t>& out, int64_t& nb) {
   CHECK_ARG(ctx, map != nullptr, "map is NULL");
   CHECK_ARG(ctx, map->n == n, "map->n (%lld) != n (%lld)", (long long)map->n, (long long)n);
   nb = map->nb;
@@ -294,6 +293,32 @@ int check_map(mpcr_ctx* ctx, int64_t n, const mpcr_tilemap_t* map, std::vector<u
       if (i == j) CHECK_ARG(ctx, p == F64, "diagonal tile %lld must be FP64", (long long)i);
     }
   return MPCR_OK;
+}
+
+// The map to factor again with after a breakdown at global column `info`
+// (1-based): the pivot of tile step k = (info-1)/nb depends on the leading
+// (k+1) x (k+1) tiles; p is the coarsest format among their off-diagonal tiles
+// and d_fail the smallest distance i - j at which p occurs there.  Every tile
+// of format p (FP16 and BF16 count as one level) with distance >= d_fail moves
+// one format up.  Returns false when the leading tiles are all FP64.
+bool promote_map(std::vector<uint8_t>& map, int64_t nt, int64_t nb, int64_t info) {
+  auto rank = [](int p) { return p == F64 ? 3 : p == F32 ? 2 : p == F8 ? 0 : 1; };
+  auto up = [](int p) { return p == F8 ? F16 : (p == F16 || p == BF16) ? F32 : F64; };
+  const int64_t k = std::min<int64_t>((info - 1) / nb, nt - 1);
+  int rmin = 3;
+  for (int64_t i = 0; i <= k; ++i)
+    for (int64_t j = 0; j < i; ++j) rmin = std::min(rmin, rank(map[i * nt + j]));
+  if (rmin == 3) return false;
+  int64_t dfail = nt;
+  for (int64_t i = 0; i <= k; ++i)
+    for (int64_t j = 0; j < i; ++j)
+      if (rank(map[i * nt + j]) == rmin) dfail = std::min(dfail, i - j);
+  for (int64_t i = 0; i < nt; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      uint8_t& p = map[i * nt + j];
+      if (rank(p) == rmin && i - j >= dfail) p = (uint8_t)up(p);
+    }
+  return true;
 }
 
 // Allocates a factor for the map and fills its task lists.
@@ -973,7 +998,7 @@ int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda, c
   CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && lda >= n && d_A, "bad n / lda / A");
   std::vector<uint8_t> m;
   int64_t nb;
-  int rc = check_map(ctx, n, map, m, nb, false);
+  int rc = check_map(ctx, n, map, m, nb);
   if (rc) return rc;
   DeviceGuard g(ctx->device);
   mpcr_factor* f = nullptr;
@@ -999,7 +1024,7 @@ int mpcr_potrf_tiled_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, 
   CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs, "bad n / locs");
   std::vector<uint8_t> m;
   int64_t nb;
-  if ((rc = check_map(ctx, n, map, m, nb, false)) != MPCR_OK) return rc;
+  if ((rc = check_map(ctx, n, map, m, nb)) != MPCR_OK) return rc;
   DeviceGuard g(ctx->device);
   mpcr_factor* f = nullptr;
   if ((rc = make_factor(ctx, n, nb, m, &f)) != MPCR_OK) return rc;
@@ -1122,41 +1147,49 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   std::vector<uint8_t> m;
   int64_t nb = 256;
   if (map) {
-    if ((rc = check_map(ctx, n, map, m, nb, false)) != MPCR_OK) return rc;
+    if ((rc = check_map(ctx, n, map, m, nb)) != MPCR_OK) return rc;
   } else {
     int64_t nt = (n + nb - 1) / nb;
     m.assign(nt * nt, 255);
     for (int64_t i = 0; i < nt; ++i)
       for (int64_t j = 0; j <= i; ++j) m[i * nt + j] = F64;
   }
-  bool all64 = true;
-  {
-    int64_t nt = (n + nb - 1) / nb;
-    for (int64_t i = 0; i < nt; ++i)
-      for (int64_t j = 0; j <= i; ++j) all64 &= (m[i * nt + j] == F64);
-  }
+  const int64_t nt = (n + nb - 1) / nb;
   if (opts) CHECK_ARG(ctx, opts->tol > 0 && opts->solver >= 0 && opts->solver <= 1 && opts->recompute >= 0 &&
-                               opts->max_iter >= 0 && (opts->residual == 0 || opts->residual == 1),
+                               opts->max_iter >= 0 && (opts->residual == 0 || opts->residual == 1) &&
+                               (opts->promote_on_breakdown == 0 || opts->promote_on_breakdown == 1) &&
+                               (opts->direct_eta == 0 || opts->direct_eta == 1),
                       "bad refinement options");
+  const bool promote = opts && opts->promote_on_breakdown;
+  const bool refine_on = opts && opts->max_iter > 0;
+  const bool stored_residual = refine_on && opts->residual == 1;
   DeviceGuard g(ctx->device);
   hipStream_t s = ctx->stream;
 
-  // workspace: factor of this shape and map, sorted sites
-  if (!ctx->ws_factor || ctx->ws_n != n || ctx->ws_nb != nb || ctx->ws_map != m) {
+  // workspace: the sorted sites (per n) and the factor (per n, nb and map)
+  if (ctx->ws_n != n) {
     free_factor(ctx->ws_factor);
     ctx->ws_factor = nullptr;
     dfree(ctx->arena, ctx->ws_locs);
     ctx->ws_locs = nullptr;
     ctx->ws_n = -1;
-    if ((rc = make_factor(ctx, n, nb, m, &ctx->ws_factor)) != MPCR_OK) return rc;
     HIP_TRY(ctx, dmalloc(ctx->arena, &ctx->ws_locs, (size_t)n * 2 * 8 + (size_t)n * 8));
     ctx->ws_n = n;
-    ctx->ws_nb = nb;
-    ctx->ws_map = m;
   }
-  mpcr_factor* f = ctx->ws_factor;
+  auto ensure_factor = [&](const std::vector<uint8_t>& mm) -> int {
+    if (ctx->ws_factor && ctx->ws_nb == nb && ctx->ws_map == mm) return MPCR_OK;
+    free_factor(ctx->ws_factor);
+    ctx->ws_factor = nullptr;
+    ctx->ws_map.clear();
+    int r = make_factor(ctx, n, nb, mm, &ctx->ws_factor);
+    if (r != MPCR_OK) return r;
+    ctx->ws_nb = nb;
+    ctx->ws_map = mm;
+    return MPCR_OK;
+  };
+  if ((rc = ensure_factor(m)) != MPCR_OK) return rc;
   SolveBufs b;
-  if ((rc = carve(ctx, f->N, nrhs, n, b)) != MPCR_OK) return rc;
+  if ((rc = carve(ctx, ctx->ws_factor->N, nrhs, n, b)) != MPCR_OK) return rc;
   double* locs = ctx->ws_locs;
   int64_t* perm = (int64_t*)(ctx->ws_locs + 2 * n);
 
@@ -1164,10 +1197,10 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   if (order) {
     int npow2 = 1;
     while (npow2 < n) npow2 <<= 1;
-    // keys live in the X block (N * nrhs * 8 >= npow2 * 8 is not guaranteed): use P..Z blocks if needed
+    // the sort keys use the P, Q, Z blocks when they are large enough
     uint64_t* keys = nullptr;
     bool own = false;
-    if ((int64_t)npow2 * 8 <= 3 * f->N * nrhs * 8) {
+    if ((int64_t)npow2 * 8 <= 3 * b.N * nrhs * 8) {
       keys = (uint64_t*)b.P;
     } else {
       HIP_TRY(ctx, dmalloc(ctx->arena, &keys, (size_t)npow2 * 8));
@@ -1188,25 +1221,40 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     HIP_TRY(ctx, launch_copy_cols((int)n, 2, d_locs, n, locs, n, s));
     HIP_TRY(ctx, launch_copy_cols((int)n, (int)nrhs, d_Z, n, b.B, b.N, s));
   }
-  HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), s));
-  const bool stored_residual = opts && opts->max_iter > 0 && opts->residual == 1;
-  if (stored_residual && !f->d_sig) {
-    HIP_TRY(ctx, dmalloc(f->arena, &f->d_sig, (size_t)(f->nt * (f->nt + 1) / 2) * f->nb * f->nb * 8));
-    HIP_TRY(ctx, dmalloc(f->arena, &f->d_rpart, residual_part_bytes((int)f->nb, (int)f->nt)));
-  }
-  if (f->has_f8) {
-    HIP_TRY(ctx, launch_covariance_tile_amax((int)n, (int)f->nb, locs, *theta, f->d_tamax, s));
-    HIP_TRY(ctx, launch_fp8_scales(f->view(), f->d_tamax, s));
-  }
-  HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s, stored_residual ? f->d_sig : nullptr));
-  HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
-  if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
-  HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+
+  // tiles and factorisation; after a breakdown, optionally promote and again
+  int promotions = 0;
   int64_t info = 0;
-  rc = read_info(ctx, f, &info);
+  for (;;) {
+    mpcr_factor* f = ctx->ws_factor;
+    HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), s));
+    if (stored_residual && !f->d_sig) {
+      HIP_TRY(ctx, dmalloc(f->arena, &f->d_sig, (size_t)(f->nt * (f->nt + 1) / 2) * f->nb * f->nb * 8));
+      HIP_TRY(ctx, dmalloc(f->arena, &f->d_rpart, residual_part_bytes((int)f->nb, (int)f->nt)));
+    }
+    if (f->has_f8) {
+      HIP_TRY(ctx, launch_covariance_tile_amax((int)n, (int)f->nb, locs, *theta, f->d_tamax, s));
+      HIP_TRY(ctx, launch_fp8_scales(f->view(), f->d_tamax, s));
+    }
+    HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s, stored_residual ? f->d_sig : nullptr));
+    if (promotions == 0) HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
+    if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+    rc = read_info(ctx, f, &info);
+    if (rc != MPCR_ERR_NOT_SPD || !promote || promotions >= 8) break;
+    std::vector<uint8_t> m2 = ctx->ws_map;
+    if (!promote_map(m2, nt, nb, info)) break;
+    ++promotions;
+    if ((rc = ensure_factor(m2)) != MPCR_OK) return rc;
+  }
+  mpcr_factor* f = ctx->ws_factor;
+  bool all64 = true;
+  for (int64_t i = 0; i < nt; ++i)
+    for (int64_t j = 0; j <= i; ++j) all64 &= (ctx->ws_map[i * nt + j] == F64);
   if (diag) {
     memset(diag, 0, sizeof *diag);
     diag->info = info;
+    diag->promotions = promotions;
     for (int p = 0; p < 5; ++p) diag->flops_by_prec[p] = f->flops[p];
   }
   if (rc) return rc;
@@ -1217,14 +1265,13 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
   HIP_TRY(ctx, launch_logdet(f->view(), d_logdet, s));
   if ((rc = ensure_linv(ctx, f)) != MPCR_OK) return rc;
   bool conv = true;
-  const bool refine_on = opts && opts->max_iter > 0;
   HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
   if (all64 && !refine_on) {
     // the paper's path: w = L^{-1} z, quad = ||w||^2, and x = L^{-T} w
     if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;
     HIP_TRY(ctx, launch_col_dot((int)n, (int)nrhs, b.W, b.W, b.N, b.partial, d_quad, s));
     HIP_TRY(ctx, hipEventRecord(ctx->ev[4], s));
-    if (diag) {  // report the backward error of the direct solve
+    if (diag && (!opts || opts->direct_eta)) {  // backward error of the direct solve
       SigmaOp op;
       op.ctx = ctx;
       op.locs = locs;
@@ -1242,10 +1289,10 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
         diag->eta = std::max(diag->eta, hst[2 * c]);
         diag->rel_resid2 = std::max(diag->rel_resid2, hst[2 * c + 1]);
       }
-      diag->converged = 1;
     }
+    if (diag) diag->converged = 1;
   } else {
-    mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0};
+    mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0, 0, 0};
     SigmaOp op;
     op.ctx = ctx;
     if (stored_residual) {
@@ -1283,6 +1330,140 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     diag->t_refine_ms = ev_ms(ctx->ev[4], ctx->ev[5]);
   }
   if (!conv) return set_err(ctx, MPCR_ERR_NOT_CONVERGED, "refinement did not reach the tolerance");
+  return MPCR_OK;
+}
+
+int mpcr_mle_fit(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_z, double nu, double nugget,
+                 const mpcr_tilemap_t* map, const mpcr_refine_opts_t* refine, const double* h_x0, int max_iter,
+                 double reltol, double* h_x_out, double* h_nll_out, int* h_iters, int* h_evals) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs && d_z && h_x0 && h_x_out && h_nll_out, "bad arguments");
+  CHECK_ARG(ctx, nu == 0.5 || nu == 1.5 || nu == 2.5, "nu must be 0.5, 1.5 or 2.5");
+  CHECK_ARG(ctx, nugget >= 0 && std::isfinite(nugget) && max_iter >= 0 && reltol >= 0, "bad nugget / options");
+  CHECK_ARG(ctx, std::isfinite(h_x0[0]) && std::isfinite(h_x0[1]), "x0 must be finite");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  // the sites and observations in Morton order, once for the whole fit
+  double* dsorted = nullptr;
+  int64_t* perm = nullptr;
+  HIP_TRY(ctx, dmalloc(ctx->arena, &dsorted, (size_t)n * 3 * 8));
+  auto release = [&] {
+    (void)hipStreamSynchronize(s);
+    dfree(ctx->arena, dsorted);
+    dfree(ctx->arena, perm);
+  };
+  hipError_t e = dmalloc(ctx->arena, &perm, (size_t)n * 8);
+  if (e != hipSuccess) {
+    release();
+    HIP_TRY(ctx, e);
+  }
+  int rc = mpcr_morton_order(ctx, n, d_locs, perm);
+  if (rc) {
+    release();
+    return rc;
+  }
+  e = launch_gather_rows((int)n, 2, d_locs, n, perm, dsorted, n, s);
+  if (e == hipSuccess) e = launch_gather_rows((int)n, 1, d_z, n, perm, dsorted + 2 * n, n, s);
+  if (e != hipSuccess) {
+    release();
+    HIP_TRY(ctx, e);
+  }
+  // f(p) = -l(range = e^p0, variance = e^p1); a breakdown of the factor is +inf
+  int fail = MPCR_OK;
+  int evals = 0;
+  auto nll = [&](const double* p) -> double {
+    if (fail) return INFINITY;
+    mpcr_theta_t th{std::exp(p[1]), std::exp(p[0]), nu, nugget};
+    if (!(th.sigma2 > 0) || !(th.range > 0) || !std::isfinite(th.sigma2) || !std::isfinite(th.range))
+      return INFINITY;
+    double ll = 0;
+    ++evals;
+    int r = mpcr_gauss_loglik(ctx, n, dsorted, dsorted + 2 * n, 1, &th, map, 0, refine, &ll, nullptr);
+    if (r == MPCR_ERR_NOT_SPD) return INFINITY;
+    if (r != MPCR_OK) {
+      fail = r;
+      return INFINITY;
+    }
+    return -ll;
+  };
+  // Nelder-Mead (reflection 1, expansion 2, contraction 1/2, shrink 1/2),
+  // first simplex x0 + s e_i with s = 0.1 max|x0_i| (0.1 for x0 = 0)
+  const double s0 = std::max(std::fabs(h_x0[0]), std::fabs(h_x0[1]));
+  const double step = s0 > 0 ? 0.1 * s0 : 0.1;
+  double pts[3][2] = {{h_x0[0], h_x0[1]}, {h_x0[0] + step, h_x0[1]}, {h_x0[0], h_x0[1] + step}};
+  double val[3];
+  for (int i = 0; i < 3; ++i) val[i] = nll(pts[i]);
+  int it = 0;
+  for (;;) {
+    int idx[3] = {0, 1, 2};
+    std::stable_sort(idx, idx + 3, [&](int a, int b) { return val[a] < val[b]; });
+    double sp[3][2], sv[3];
+    for (int i = 0; i < 3; ++i) {
+      sp[i][0] = pts[idx[i]][0];
+      sp[i][1] = pts[idx[i]][1];
+      sv[i] = val[idx[i]];
+    }
+    memcpy(pts, sp, sizeof pts);
+    memcpy(val, sv, sizeof val);
+    if (fail || val[2] - val[0] <= reltol * (std::fabs(val[0]) + reltol) || it >= max_iter) break;
+    ++it;
+    const double c[2] = {0.5 * (pts[0][0] + pts[1][0]), 0.5 * (pts[0][1] + pts[1][1])};
+    const double xr[2] = {c[0] + (c[0] - pts[2][0]), c[1] + (c[1] - pts[2][1])};
+    const double fr = nll(xr);
+    auto take = [&](const double* x, double fx) {
+      pts[2][0] = x[0];
+      pts[2][1] = x[1];
+      val[2] = fx;
+    };
+    if (val[0] <= fr && fr < val[1]) {
+      take(xr, fr);
+      continue;
+    }
+    if (fr < val[0]) {
+      const double xe[2] = {c[0] + 2.0 * (xr[0] - c[0]), c[1] + 2.0 * (xr[1] - c[1])};
+      const double fe = nll(xe);
+      if (fe < fr) take(xe, fe);
+      else take(xr, fr);
+      continue;
+    }
+    if (fr < val[2]) {
+      const double xc[2] = {c[0] + 0.5 * (xr[0] - c[0]), c[1] + 0.5 * (xr[1] - c[1])};
+      const double fc = nll(xc);
+      if (fc <= fr) {
+        take(xc, fc);
+        continue;
+      }
+    } else {
+      const double xcc[2] = {c[0] - 0.5 * (c[0] - pts[2][0]), c[1] - 0.5 * (c[1] - pts[2][1])};
+      const double fcc = nll(xcc);
+      if (fcc < val[2]) {
+        take(xcc, fcc);
+        continue;
+      }
+    }
+    for (int i = 1; i < 3; ++i) {
+      pts[i][0] = pts[0][0] + 0.5 * (pts[i][0] - pts[0][0]);
+      pts[i][1] = pts[0][1] + 0.5 * (pts[i][1] - pts[0][1]);
+      val[i] = nll(pts[i]);
+    }
+  }
+  release();
+  if (fail) return fail;
+  h_x_out[0] = pts[0][0];
+  h_x_out[1] = pts[0][1];
+  *h_nll_out = val[0];
+  if (h_iters) *h_iters = it;
+  if (h_evals) *h_evals = evals;
+  return MPCR_OK;
+}
+
+int mpcr_loglik_map(const mpcr_ctx* ctx, int64_t* h_nt, uint8_t* h_map_out, int64_t capacity) {
+  if (!ctx || !h_nt) return MPCR_ERR_ARG;
+  if (!ctx->ws_factor || ctx->ws_map.empty()) return MPCR_ERR_ARG;
+  const int64_t nt = ctx->ws_factor->nt;
+  *h_nt = nt;
+  if (!h_map_out || capacity < nt * nt) return MPCR_ERR_ARG;
+  memcpy(h_map_out, ctx->ws_map.data(), (size_t)(nt * nt));
   return MPCR_OK;
 }
 

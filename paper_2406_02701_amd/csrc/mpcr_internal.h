@@ -28,9 +28,10 @@ __host__ __device__ inline double fmt_unit_roundoff(int f) {
   return f == F64 ? 0x1p-53 : f == F32 ? 0x1p-24 : f == F16 ? 0x1p-11 : f == BF16 ? 0x1p-8 : 0x1p-4;
 }
 // Half the smallest subnormal: the absolute rounding error of values below the
-// normal range (FP8 is scaled per block or tile, so its floor is relative).
+// normal range (FP8 is scaled per block or tile, so its floor is relative;
+// FP64's, 2^-1075, is not representable and lies far below every guard).
 __host__ __device__ inline double fmt_abs_floor(int f) {
-  return f == F64 ? 0x1p-1075 : f == F32 ? 0x1p-150 : f == F16 ? 0x1p-25 : f == BF16 ? 0x1p-134 : 0.0;
+  return f == F32 ? 0x1p-150 : f == F16 ? 0x1p-25 : f == BF16 ? 0x1p-134 : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -130,7 +130,7 @@ void run_request(mpcr_server* srv, mpcr_ctx* ctx, Request& r, Done& d) {
   if (rc == MPCR_OK) {
     mpcr_tilemap_t tm{n, o.nb, (n + o.nb - 1) / o.nb, map.data()};
     rc = mpcr_gauss_loglik(ctx, n, dls, dzs, 1, &r.theta, &tm, 0, &o.refine, &d.loglik, &d.diag);
-    if (rc == MPCR_ERR_NOT_SPD && o.fallback_fp64) {
+    if (rc == MPCR_ERR_NOT_SPD && o.fallback_fp64) {  // last resort after any promotions
       for (auto& v : map)
         if (v != 255) v = MPCR_FP64;
       d.fallback = 1;
@@ -201,8 +201,13 @@ int mpcr_serve_create(int device, size_t hbm_budget, int max_slots, const mpcr_s
   if (opts->nb < 128 || opts->nb % 128 || opts->band_fp64 < 0 || opts->band_fp32 < opts->band_fp64 ||
       !(opts->far_prec == MPCR_FP16 || opts->far_prec == MPCR_BF16 || opts->far_prec == MPCR_FP32 ||
         opts->far_prec == MPCR_FP64) ||
-      !(opts->refine.tol > 0) || opts->refine.max_iter < 0)
+      !(opts->refine.tol > 0) || opts->refine.max_iter < 0 || opts->refine.solver < 0 || opts->refine.solver > 1 ||
+      opts->refine.recompute < 0 || (opts->refine.promote_on_breakdown != 0 && opts->refine.promote_on_breakdown != 1) ||
+      (opts->refine.direct_eta != 0 && opts->refine.direct_eta != 1))
     return MPCR_ERR_ARG;
+  // the stored FP64 residual doubles a request's device footprint, which the
+  // admission estimate does not cover: requests regenerate Sigma from the sites
+  if (opts->refine.residual != 0) return MPCR_ERR_ARG;
   *out = nullptr;
   auto* srv = new mpcr_server();
   srv->device = device;

@@ -39,14 +39,14 @@ class mpcr_theta_t(C.Structure):
 
 class mpcr_refine_opts_t(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("solver", C.c_int), ("recompute", C.c_int),
-                ("residual", C.c_int)]
+                ("residual", C.c_int), ("promote_on_breakdown", C.c_int), ("direct_eta", C.c_int)]
 
 
 class mpcr_diag_t(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("eta", C.c_double), ("rel_resid2", C.c_double),
                 ("logdet", C.c_double), ("quad0", C.c_double), ("info", C.c_int64),
                 ("t_gen_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_refine_ms", C.c_double), ("flops_by_prec", C.c_double * 5)]
+                ("t_refine_ms", C.c_double), ("flops_by_prec", C.c_double * 5), ("promotions", C.c_int)]
 
 
 # The library must share the process's HIP runtime with PyTorch, which ships its
@@ -94,6 +94,9 @@ _SIGS = {
                           _P(mpcr_diag_t)]),
     "mpcr_gauss_loglik": (_i32, [_vp, _i64, _vp, _vp, _i64, _P(mpcr_theta_t), _P(mpcr_tilemap_t), _i32,
                                  _P(mpcr_refine_opts_t), _P(_d), _P(mpcr_diag_t)]),
+    "mpcr_loglik_map": (_i32, [_vp, _P(_i64), _P(C.c_uint8), _i64]),
+    "mpcr_mle_fit": (_i32, [_vp, _i64, _vp, _vp, _d, _d, _P(mpcr_tilemap_t), _P(mpcr_refine_opts_t), _P(_d), _i32,
+                            _d, _P(_d), _P(_d), _P(_i32), _P(_i32)]),
     "mpcr_convert": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mpcr_serve_create": (_i32, [_i32, C.c_size_t, _i32, _P(mpcr_serve_opts_t), _P(_vp)]),
     "mpcr_serve_destroy": (_i32, [_vp]),

@@ -13,7 +13,7 @@ import numpy as np
 
 __all__ = [
     "rng", "locations", "normal_rhs", "uniform_matrix", "integer_matrix",
-    "grid_1d", "serving_requests", "WORKLOADS",
+    "grid_1d", "grid_2d", "serving_requests", "WORKLOADS",
 ]
 
 
@@ -46,6 +46,16 @@ def grid_1d(n: int, spacing: float) -> np.ndarray:
     """n points on a regular 1-D grid along the x axis (y = 0), n x 2."""
     out = np.zeros((n, 2))
     out[:, 0] = np.arange(n, dtype=np.float64) * spacing
+    return out
+
+
+def grid_2d(m: int) -> np.ndarray:
+    """The m x m regular grid on the unit square, points (i/(m-1), j/(m-1)),
+    x varying fastest (the layout of R's expand.grid), as an m^2 x 2 array."""
+    t = np.arange(m, dtype=np.float64) / (m - 1)
+    out = np.empty((m * m, 2))
+    out[:, 0] = np.tile(t, m)
+    out[:, 1] = np.repeat(t, m)
     return out
 
 
@@ -90,6 +100,11 @@ WORKLOADS = {
                          map="band", bands=((2, "fp64"), (8, "fp32"), (None, "bf16"))),
     # Serving stream.
     "serve_4096": dict(count=4096, seed=6, n_lo=256, n_hi=8192, nb=256),
+    # Maximum likelihood fit on a regular grid (the MLE example's 120 x 120
+    # grid, exponential covariance, variance 1, range 0.03, nu fixed at 1/2,
+    # optimiser started from p = (log range, log variance) = (1.5, -0.3)).
+    "mle_grid120": dict(m=120, nu=0.5, sigma2=1.0, range=0.03, nugget=0.0, seed_z=1234, x0=(1.5, -0.3),
+                        max_iter=1000, reltol=1e-8),
     # Large mixed factor, n = 65536, nb = 1024, Matérn 5/2.
     "mixed_n65536": dict(n=65536, nb=1024, nrhs=256, nu=2.5, sigma2=1.0, range=0.05,
                          nugget=1e-6, seed_locs=7, seed_z=8,

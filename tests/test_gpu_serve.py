@@ -9,6 +9,12 @@
   complete (they wait in the queue).
 * Results agree with the FP64 oracle log-likelihood (mixed map refined to
   eta <= 1e-13; the factor's log-determinant carries the low tiles' error).
+* Requests of 1600-3000 sites whose norm-guarded maps keep BF16 tiles at
+  nb = 256: the quadratic form is the FP64 one and the served
+  log-determinant lies within the emulated mixed factor's shift from the FP64
+  log-determinant of the emulated value.
+* Options the footprint estimate does not cover (the stored FP64 residual)
+  are rejected at create.
 """
 import ctypes
 import time
@@ -20,7 +26,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import synth  # noqa: E402
+from oracle import covariance as cov  # noqa: E402
 from oracle import loglik as olog  # noqa: E402
+from oracle import tiled  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +40,7 @@ def mp():
 
 
 def opts(mp, nb=256):
-    return mp.mpcr_serve_opts_t(nb, 1, 4, mp.MPCR_BF16, 0.01, mp.mpcr_refine_opts_t(1e-13, 100, 0, 20, 0), 1)
+    return mp.mpcr_serve_opts_t(nb, 1, 4, mp.MPCR_BF16, 0.01, mp.mpcr_refine_opts_t(1e-13, 100, 0, 20, 0, 1), 1)
 
 
 def requests(count, seed, n_lo, n_hi):
@@ -131,3 +139,47 @@ def test_serving_matches_oracle(mp):
         ref = olog.loglik_plain(lo, zo, r["sigma2"], r["range"], r["nu"], r["nugget"])["loglik"][0]
         assert res[i]["status"] == 0
         assert abs(res[i]["ll"] - ref) <= 1e-6 * abs(ref), (i, res[i]["ll"], ref, r)
+
+
+def test_serving_bf16_tiles_match_emulation(mp):
+    cases = [(2048, 0.02, 0.5, 701), (2048, 0.03, 1.5, 702), (3000, 0.02, 2.5, 703), (1600, 0.02, 0.5, 704)]
+    srv = make_server(mp, 8 << 30, 4)
+    data = []
+    for i, (n, rng_, nu, seed) in enumerate(cases):
+        locs = np.asfortranarray(synth.locations(n, seed))
+        z = np.ascontiguousarray(synth.normal_rhs(n, 1, seed + 1000)[:, 0])
+        r = dict(n=n, sigma2=1.0, range=rng_, nu=nu, nugget=1e-6)
+        assert submit(mp, srv, i, r, locs, z) == 0
+        data.append((r, locs, z))
+    got = {}
+    for _ in cases:
+        rid, ll, st, fb = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+        diag = mp.mpcr_diag_t()
+        t0 = time.time()
+        while mp.mpcr_serve_poll(srv, ctypes.byref(rid), ctypes.byref(ll), ctypes.byref(diag), None, None,
+                                 ctypes.byref(st), ctypes.byref(fb)) != 1:
+            assert time.time() - t0 < 240
+            time.sleep(0.002)
+        got[rid.value] = (ll.value, st.value, fb.value, diag.logdet, diag.quad0, diag.promotions)
+    mp.mpcr_serve_destroy(srv)
+    for i, (r, locs, z) in enumerate(data):
+        ll, st, fb, ld, q, promos = got[i]
+        assert st == 0 and fb == 0 and promos == 0, got[i]
+        lo, zo, _ = olog.order_sites(locs, z[:, None])
+        S = cov.covariance(lo, 1.0, r["range"], r["nu"], 1e-6)
+        banded = tiled.tilemap_banded(r["n"], 256, ((1, "fp64"), (4, "fp32"), (None, "bf16")))
+        gm = tiled.tilemap_guarded(banded, tiled.tile_amax(S, 256), 0.01 * 1e-6)
+        assert np.any(gm == mp.MPCR_BF16)
+        emu = olog.loglik_mixed(lo, zo, 1.0, r["range"], r["nu"], 1e-6, 256, gm, tol=1e-13)
+        plain = olog.loglik_plain(lo, zo, 1.0, r["range"], r["nu"], 1e-6)
+        assert abs(q - plain["quad"][0]) <= 1e-9 * abs(plain["quad"][0])
+        shift = abs(emu["logdet"] - plain["logdet"])
+        print(f"request {i}: logdet {ld!r} emulated {emu['logdet']!r} fp64 {plain['logdet']!r}", flush=True)
+        assert abs(ld - emu["logdet"]) <= max(shift, 1e-9 * abs(plain["logdet"]))
+
+
+def test_serving_rejects_stored_residual(mp):
+    srv = ctypes.c_void_p()
+    o = opts(mp)
+    o.refine.residual = 1
+    assert mp.mpcr_serve_create(0, 1 << 30, 2, ctypes.byref(o), ctypes.byref(srv)) == mp.MPCR_ERR_ARG

@@ -410,6 +410,44 @@ def test_literal_bf16_band_map_breaks_down(g):
     assert 1 <= diag.info <= n
 
 
+def test_promote_on_breakdown_matches_oracle(g):
+    """The literal BF16 band map breaks down on this Matern 3/2 covariance; with
+    promote_on_breakdown the library refactors with promoted tiles.  The map it
+    ends with is the oracle's (the promotion rule depends on the breakdown's
+    tile step only through the leading block's coarsest format and its
+    smallest distance), the quadratic form refines to the FP64 one and the
+    log-determinant lies within the emulated factor's shift from the FP64
+    log-determinant of the emulated value (the GPU accumulates the FP32
+    tiles' updates in FP32, which perturbs the factor about as much as the
+    tile roundings the emulation models)."""
+    gu, ctx = g
+    from paper_2406_02701_amd import mpcr
+    n, nb = 2048, 128
+    locs = synth.locations(n, 4)
+    z = synth.normal_rhs(n, 1, 5)
+    th = gu.theta(1.0, 0.05, 1.5, 1e-6)
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (4, "fp32"), (None, "bf16")))
+    opts = mpcr.mpcr_refine_opts_t(1e-13, 100, 0, 20, 0, 1)
+    st, ll, diag = _loglik(gu, ctx, locs, z, th, nb, m, order=1, opts=opts)
+    ctx.check(st)
+    assert diag.promotions >= 1 and diag.converged == 1
+    nt = ctypes.c_int64()
+    used = np.zeros((m.shape[0], m.shape[0]), np.uint8)
+    ctx.check(mpcr.mpcr_loglik_map(ctx.ptr, ctypes.byref(nt), used.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   used.size))
+    lo, zo, _ = loglik.order_sites(locs, z)
+    emu = loglik.loglik_mixed(lo, zo, 1.0, 0.05, 1.5, 1e-6, nb, m, tol=1e-13, promote=True)
+    assert emu["info"] == 0
+    tri = np.tril_indices(m.shape[0])
+    assert np.array_equal(used[tri], emu["map"][tri])
+    assert diag.promotions == emu["promotions"]
+    ref = loglik.loglik_plain(lo, zo, 1.0, 0.05, 1.5, 1e-6)
+    assert abs(diag.quad0 - ref["quad"][0]) <= 1e-9 * abs(ref["quad"][0])
+    shift = abs(emu["logdet"] - ref["logdet"])
+    print(f"promotion: logdet {diag.logdet!r} emulated {emu['logdet']!r} fp64 {ref['logdet']!r}", flush=True)
+    assert abs(diag.logdet - emu["logdet"]) <= max(shift, 1e-9 * abs(ref["logdet"]))
+
+
 def test_stored_and_matrix_free_residuals_agree(g):
     """Refinement with the FP64 residual streamed from a stored copy of Sigma's
     tiles reaches the same log-likelihood as regenerating Sigma from the sites.

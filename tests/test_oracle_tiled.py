@@ -244,3 +244,115 @@ def test_three_tile_step_by_hand_fp8():
     L22 = np.linalg.cholesky(A22 - L21 @ L21.T)
     for (i, j, ref) in [(0, 0, L00), (1, 0, L10), (2, 0, L20), (1, 1, L11), (2, 1, L21), (2, 2, L22)]:
         np.testing.assert_allclose(t(out, i, j), ref, rtol=1e-13, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# norm-guarded map and promotion after a breakdown
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8_e4m3"])
+@pytest.mark.parametrize("amax", [0.7, 3e-5, 2e-8])
+def test_rounding_bound_holds_and_is_attained(fmt, amax):
+    """rounding_bound(p, amax) bounds |round(x) - x| for every |x| <= amax
+    (an FP8 tile is rounded with its own power-of-two scale), and half of it is
+    reached: a wrong unit roundoff or subnormal floor fails one of the two."""
+    code = ff.CODE[fmt]
+    rng = np.random.default_rng(5)
+    x = amax * rng.uniform(-1, 1, 200000)
+    x[0] = amax
+    err = np.abs(tiled.round_tile(x, code) - x)
+    b = tiled.rounding_bound(code, amax)
+    assert err.max() <= b
+    assert err.max() >= 0.5 * b
+
+
+def test_guarded_map_hand_example():
+    """3 x 3 and 2 x 2 tile examples worked out by hand with guard 1e-8."""
+    F64, F32, F16, BF16, F8 = (ff.CODE[k] for k in ("fp64", "fp32", "fp16", "bf16", "fp8_e4m3"))
+    U = tiled.UNUSED
+    banded = np.array([[F64, U, U], [F32, F64, U], [BF16, F32, F64]], np.uint8)
+    amax = np.array([[1, 0, 0], [0.5, 1, 0], [1e-9, 1e-3, 1]])
+    # (1,0): 2^-24 * 0.5 = 3.0e-8 > 1e-8 -> FP64; (2,1): 2^-24 * 1e-3 = 6e-11 -> FP32;
+    # (2,0): 2^-8 * 1e-9 = 3.9e-12 -> BF16
+    got = tiled.tilemap_guarded(banded, amax, 1e-8)
+    assert got.tolist() == [[F64, U, U], [F64, F64, U], [BF16, F32, F64]]
+    # FP16 tile of magnitude 1e-7: relative 4.9e-11 but values below 2^-14 round
+    # with absolute error up to 2^-25 = 3.0e-8 > 1e-8 -> FP32.
+    # FP8 tile (own scale) of magnitude 1e-7: 2^-4 * 1e-7 = 6.25e-9 -> stays FP8;
+    # of magnitude 1e-6: 6.25e-8 -> FP16 -> floor 3.0e-8 -> FP32.
+    banded = np.array([[F64, U], [F16, F64]], np.uint8)
+    assert tiled.tilemap_guarded(banded, np.array([[1, 0], [1e-7, 1]]), 1e-8)[1, 0] == F32
+    banded = np.array([[F64, U], [F8, F64]], np.uint8)
+    assert tiled.tilemap_guarded(banded, np.array([[1, 0], [1e-7, 1]]), 1e-8)[1, 0] == F8
+    assert tiled.tilemap_guarded(banded, np.array([[1, 0], [1e-6, 1]]), 1e-8)[1, 0] == F32
+    # magnitude 1e-2, guard 1e-4: FP8 6.25e-4 is too coarse, FP16 4.9e-6 is not
+    assert tiled.tilemap_guarded(banded, np.array([[1, 0], [1e-2, 1]]), 1e-4)[1, 0] == F16
+
+
+def test_guarded_map_is_the_first_format_meeting_the_guard():
+    n, nb = 2048, 128
+    locs = synth.locations(n, 4)
+    S = cov.covariance(locs[cov.morton_order(locs)], 1.0, 0.05, 1.5, 1e-6)
+    amax = tiled.tile_amax(S, nb)
+    # tile maxima by a plain scan
+    t = S[3 * nb:4 * nb, 1 * nb:2 * nb]
+    assert amax[3, 1] == np.abs(t).max()
+    banded = tiled.tilemap_banded(n, nb, ((1, "fp64"), (4, "fp32"), (8, "fp16"), (None, "fp8_e4m3")))
+    for guard in (1e-6, 1e-8, 1e-10):
+        gm = tiled.tilemap_guarded(banded, amax, guard)
+        ladder = {ff.CODE["fp8_e4m3"]: ["fp8_e4m3", "fp16", "fp32", "fp64"], ff.CODE["fp16"]: ["fp16", "fp32", "fp64"],
+                  ff.CODE["fp32"]: ["fp32", "fp64"], ff.CODE["fp64"]: ["fp64"]}
+        for i in range(gm.shape[0]):
+            for j in range(i + 1):
+                ok = [f for f in ladder[int(banded[i, j])] if f == "fp64" or
+                      tiled.rounding_bound(ff.CODE[f], amax[i, j]) <= guard]
+                assert gm[i, j] == ff.CODE[ok[0]]
+
+
+def test_promote_after_breakdown_hand_examples():
+    F64, F32, F16, BF16, F8 = (ff.CODE[k] for k in ("fp64", "fp32", "fp16", "bf16", "fp8_e4m3"))
+    U = tiled.UNUSED
+    m = np.array([[F64, U, U, U],
+                  [F32, F64, U, U],
+                  [BF16, F32, F64, U],
+                  [BF16, BF16, F32, F64]], np.uint8)
+    # nb = 2, info = 5 -> tile step 2; leading tiles (1,0) FP32, (2,0) BF16,
+    # (2,1) FP32: coarsest BF16 at distance 2 -> every BF16 tile with d >= 2
+    # ((2,0), (3,0), (3,1)) becomes FP32
+    got = tiled.promote_after_breakdown(m, 2, 5)
+    assert got.tolist() == [[F64, U, U, U], [F32, F64, U, U], [F32, F32, F64, U], [F32, F32, F32, F64]]
+    # again at the same step: now FP32 is the coarsest, first at distance 1
+    got2 = tiled.promote_after_breakdown(got, 2, 5)
+    assert all(got2[i, j] == F64 for i in range(4) for j in range(i + 1))
+    # nothing left to promote
+    assert np.array_equal(tiled.promote_after_breakdown(got2, 2, 5), got2)
+    # FP8 far tiles, breakdown in step 3: only FP8 tiles at distance >= 3 move (to FP16)
+    m = np.array([[F64, U, U, U],
+                  [F32, F64, U, U],
+                  [F16, F32, F64, U],
+                  [F8, F16, F32, F64]], np.uint8)
+    got = tiled.promote_after_breakdown(m, 4, 13)
+    assert got[3, 0] == F16 and np.array_equal(np.delete(got.ravel(), 12), np.delete(m.ravel(), 12))
+    # breakdown in step 1: the leading block holds only (1,0) FP32
+    got = tiled.promote_after_breakdown(m, 4, 7)
+    assert got[1, 0] == F64 and got[2, 1] == F64 and got[3, 2] == F64
+    assert got[2, 0] == F16 and got[3, 0] == F8
+
+
+def test_promotion_recovers_a_breakdown_and_refines_to_fp64():
+    """The BF16 far band makes this Matern 3/2 covariance's stored tiles
+    indefinite; promoting after the breakdown gives a factor, and the refined
+    quadratic form is the FP64 one."""
+    n, nb = 1024, 128
+    locs = synth.locations(n, 4)
+    z = synth.normal_rhs(n, 1, 5)
+    lo, zo, _ = loglik.order_sites(locs, z)
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (2, "fp32"), (None, "bf16")))
+    plain = loglik.loglik_mixed(lo, zo, 1.0, 0.05, 1.5, 1e-6, nb, m, tol=1e-13)
+    assert plain["info"] > 0
+    out = loglik.loglik_mixed(lo, zo, 1.0, 0.05, 1.5, 1e-6, nb, m, tol=1e-13, promote=True)
+    assert out["info"] == 0 and out["promotions"] >= 1 and out["converged"]
+    ref = loglik.loglik_plain(lo, zo, 1.0, 0.05, 1.5, 1e-6)
+    assert abs(out["quad"][0] - ref["quad"][0]) <= 1e-8 * abs(ref["quad"][0])
+    used = out["map"]
+    assert all(used[i, j] >= 0 for i in range(used.shape[0]) for j in range(i + 1))
