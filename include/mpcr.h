@@ -204,6 +204,17 @@ int mpcr_tilemap_guarded(int64_t n, int64_t nb, const uint8_t* h_banded_map,
  * Nearby sites get nearby indices, which is what a band map relies on. */
 int mpcr_morton_order(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d_perm_out);
 
+/* The same permutation as mpcr_morton_order, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the sort keys live in a static device array owned by
+ * the library (2^20 keys, 8 MiB on each GPU the library runs on, held until
+ * the process ends), so n <= 1048576; MPCR_ERR_ARG otherwise.  The call
+ * allocates nothing and does not synchronise: the permutation is ready in
+ * stream order on the context's stream.  Every call on one GPU uses the same
+ * array, so calls that overlap on a GPU (other streams or threads) race:
+ * order them. */
+int mpcr_morton_order_noalloc(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d_perm_out);
+
 /* Dense FP64 covariance Sigma(theta) (n x n, column-major, ld >= n) from the
  * sites d_locs (n x 2 column-major), both triangles written. */
 int mpcr_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* theta,

@@ -93,6 +93,7 @@ struct mpcr_ctx {
   double* ws_vec = nullptr;       // vector workspace
   int64_t ws_vec_bytes = 0;
   uint8_t* ws_gemm = nullptr;     // packed 16/8-bit GEMM operands
+  uint64_t* noalloc_keys = nullptr;  // device address of the static sort-key array on this device
   int64_t ws_gemm_bytes = 0;
   hipEvent_t ev[6] = {};
   // kernel timing (see mpcr_ctx_set_profiling)
@@ -817,6 +818,10 @@ int mpcr_ctx_create(int device, void* hip_stream, mpcr_ctx** out) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   DeviceGuard g(device);
+  if ((e = morton_noalloc_keys(device, &c->noalloc_keys)) != hipSuccess) {
+    delete c;
+    return set_err(nullptr, MPCR_ERR_DEVICE, "hipGetSymbolAddress: %s", hipGetErrorString(e));
+  }
   for (auto& ev : c->ev)
     if ((e = hipEventCreate(&ev)) != hipSuccess) {
       delete c;
@@ -946,6 +951,25 @@ int mpcr_morton_order(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d
   if (e == hipSuccess) e = launch_keys_to_perm((int)n, keys, d_perm_out, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dfree(ctx->arena, keys);
+  HIP_TRY(ctx, e);
+  return MPCR_OK;
+}
+
+int mpcr_morton_order_noalloc(mpcr_ctx* ctx, int64_t n, const double* d_locs, int64_t* d_perm_out) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, n >= 0 && n <= MORTON_NOALLOC_MAX_KEYS, "n must be <= %d for the allocation-free ordering",
+            MORTON_NOALLOC_MAX_KEYS);
+  CHECK_ARG(ctx, n == 0 || (d_locs && d_perm_out), "NULL pointer");
+  if (n == 0) return MPCR_OK;
+  CHECK_ARG(ctx, ctx->noalloc_keys != nullptr, "sort-key array not set up");
+  DeviceGuard g(ctx->device);
+  int npow2 = 1;
+  while (npow2 < n) npow2 <<= 1;
+  // every key slot below npow2 is written by the key kernel: nothing to clear
+  hipStream_t s = ctx->stream;
+  hipError_t e = launch_morton_codes((int)n, d_locs, ctx->noalloc_keys, npow2, s);
+  if (e == hipSuccess) e = launch_bitonic_sort(ctx->noalloc_keys, npow2, s);
+  if (e == hipSuccess) e = launch_keys_to_perm((int)n, ctx->noalloc_keys, d_perm_out, s);
   HIP_TRY(ctx, e);
   return MPCR_OK;
 }

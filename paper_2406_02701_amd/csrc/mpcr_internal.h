@@ -291,6 +291,11 @@ hipError_t launch_loglik(int n, int nrhs, const double* logdet, const double* qu
 hipError_t launch_quad_refined(int n, int nrhs, const double* Z, const double* X, const double* R, int64_t ld,
                                double* partial, double* quad, hipStream_t s);
 
+// Allocation-free ordering: the sort keys live in a static device array of
+// MORTON_NOALLOC_MAX_KEYS entries (8 MiB per GPU).
+constexpr int MORTON_NOALLOC_MAX_KEYS = 1 << 20;
+constexpr int MAX_DEVICES = 64;
+hipError_t morton_noalloc_keys(int device, uint64_t** out);
 hipError_t launch_morton_codes(int n, const double* locs, uint64_t* keys, int npow2, hipStream_t s);
 hipError_t launch_bitonic_sort(uint64_t* keys, int npow2, hipStream_t s);
 hipError_t launch_keys_to_perm(int n, const uint64_t* keys, int64_t* perm, hipStream_t s);

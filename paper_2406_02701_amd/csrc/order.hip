@@ -5,9 +5,38 @@
 // q = min(floor(65536 x), 65535), and the bits are interleaved (x in the even
 // positions, y in the odd ones).  Keys (code << 32 | index) are unique, so a
 // bitonic sort of the keys gives the stable order by code.
+#include <mutex>
+
 #include "mpcr_internal.h"
 
 namespace mpcr {
+
+// Sort keys of the allocation-free ordering entry point: a library-owned
+// device array (one copy per GPU, alive until the process ends) holding up
+// to MORTON_NOALLOC_MAX_KEYS keys, i.e. orders of up to that many sites.
+static __device__ __align__(256) uint64_t scratch[MORTON_NOALLOC_MAX_KEYS];
+
+// Device address of `scratch` on `device`, looked up once per device with that
+// device current (the host-side name of the array is not a device address).
+hipError_t morton_noalloc_keys(int device, uint64_t** out) {
+  static std::mutex mu;
+  static uint64_t* addr[MAX_DEVICES] = {};
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[device]) {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return e;
+    addr[device] = (uint64_t*)p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 __device__ __forceinline__ uint32_t spread_bits16(uint32_t v) {
   v &= 0xffffu;

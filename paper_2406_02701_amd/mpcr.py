@@ -80,6 +80,7 @@ _SIGS = {
     "mpcr_tilemap_banded": (_i32, [_i64, _i64, _P(_i32), _P(_i32), _i32, _P(C.c_uint8)]),
     "mpcr_tilemap_guarded": (_i32, [_i64, _i64, _P(C.c_uint8), _P(_d), _d, _P(C.c_uint8)]),
     "mpcr_morton_order": (_i32, [_vp, _i64, _vp, _vp]),
+    "mpcr_morton_order_noalloc": (_i32, [_vp, _i64, _vp, _vp]),
     "mpcr_covariance": (_i32, [_vp, _i64, _vp, _P(mpcr_theta_t), _vp, _i64]),
     "mpcr_covariance_tile_amax": (_i32, [_vp, _i64, _i64, _vp, _P(mpcr_theta_t), _P(_d)]),
     "mpcr_potrf_tiled": (_i32, [_vp, _i64, _vp, _i64, _P(mpcr_tilemap_t), _P(_vp), _P(_i64)]),
