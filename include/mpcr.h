@@ -322,6 +322,33 @@ int mpcr_mle_fit(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d
                  const mpcr_tilemap_t* map, const mpcr_refine_opts_t* refine, const double* h_x0, int max_iter,
                  double reltol, double* h_x_out, double* h_nll_out, int* h_iters, int* h_evals);
 
+/* Laplace approximation of a latent Gaussian model with Bernoulli observations
+ * (the paper's "Integrated Nested Multi-Precision Arithmetic Laplace
+ * Approximation" section, a dense analogue of INLA): latent field
+ * x ~ N(0, Sigma(theta)) at the sites d_locs (n x 2, column-major), with
+ * Sigma the Matern covariance of variance sigma2, smoothness nu and range r
+ * (no nugget), and observations d_y (n, 0 or 1) with P(y_i = 1) =
+ * 1 / (1 + exp(-beta x_i)).  For every range r = h_range[i] the call finds the
+ * mode x0 of p(x | y) by Newton's method from x = 0 (stop when the mean
+ * squared change of x is below newton_tol; more than max_newton steps is
+ * MPCR_ERR_NOT_CONVERGED) and returns in h_lpost[i] the section's
+ *   log p(y | x0) + log|Q|/2 - x0^T Q x0 / 2 - log|Q + W|/2,
+ * Q = Sigma^-1 and W = -d^2 log p(y | x)/dx^2 at x0 (diagonal).  The
+ * precision matrix is never formed: each Newton step factors
+ * B = I + W^1/2 Sigma W^1/2 (tile map `map`, NULL = all FP64 with nb 256; a
+ * mixed map stores B's off-diagonal tiles in low precision, with unrefined
+ * solves), so log|Q| - log|Q + W| = -log|B| and, with x0 = Sigma a,
+ * x0^T Q x0 = a^T x0.  If h_posterior is not NULL the ranges must be
+ * equally spaced, increasing and odd in number, and h_posterior receives
+ * exp(l_i - mean l) normalised by Simpson's rule over the grid (the
+ * section's posterior of the range).  h_newton_iters (may be NULL) receives
+ * the Newton steps per range; d_mode_out (device, n; may be NULL) the mode at
+ * the last range.  Host arrays have nrange entries. */
+int mpcr_inla_posterior(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_y, double sigma2, double nu,
+                        double beta, const double* h_range, int nrange, double newton_tol, int max_newton,
+                        const mpcr_tilemap_t* map, double* h_lpost, double* h_posterior, int* h_newton_iters,
+                        double* d_mode_out);
+
 /* ---- matrix product ----------------------------------------------------------- */
 
 /* Round an FP64 matrix (m x n, column-major, lds) once to format `prec`

@@ -799,6 +799,81 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
 }
 }  // namespace mpcr
 
+namespace {
+// One Laplace evaluation at theta (see mpcr_inla_posterior): Newton iterations
+// for the mode of p(x | y) with B = I + W^1/2 Sigma W^1/2 factored in the tile
+// store, then l(theta) = log p(y | x) - x^T Sigma^-1 x / 2 - log|B| / 2.
+int laplace_one(mpcr_ctx* ctx, int64_t n, int64_t nb, const std::vector<uint8_t>& m, const double* d_locs,
+                const double* d_y, const mpcr_theta_t& th, double beta, double tol, int max_newton, double* vec,
+                double* h_lpost, int* h_iters) {
+  hipStream_t s = ctx->stream;
+  if (!ctx->ws_factor || ctx->ws_factor->n != n || ctx->ws_nb != nb || ctx->ws_map != m) {
+    free_factor(ctx->ws_factor);
+    ctx->ws_factor = nullptr;
+    ctx->ws_map.clear();
+    int r = make_factor(ctx, n, nb, m, &ctx->ws_factor);
+    if (r != MPCR_OK) return r;
+    ctx->ws_nb = nb;
+    ctx->ws_map = m;
+  }
+  mpcr_factor* f = ctx->ws_factor;
+  SolveBufs b;
+  int rc = carve(ctx, f->N, 1, n, b);
+  if (rc) return rc;
+  double *x = vec, *g = vec + n, *sw = vec + 2 * n, *lik = vec + 3 * n, *rhs = vec + 4 * n, *t = vec + 5 * n,
+         *a = vec + 6 * n, *xn = vec + 7 * n, *d = vec + 8 * n, *ones = vec + 9 * n, *red = vec + 10 * n;
+  double* partial = b.partial;
+  HIP_TRY(ctx, launch_fill(x, n, 0.0, s));
+  HIP_TRY(ctx, launch_fill(ones, n, 1.0, s));
+  SigmaOp op;
+  op.ctx = nullptr;
+  op.locs = d_locs;
+  op.th = th;
+  op.n = (int)n;
+  auto factor_B = [&]() -> int {
+    HIP_TRY(ctx, hipMemsetAsync(f->d_info, 0, sizeof(int), s));
+    HIP_TRY(ctx, launch_tiles_from_weighted_covariance(f->view(), d_locs, th, sw, s));
+    int r = run_factorisation(ctx, f);
+    if (r) return r;
+    int64_t info = 0;
+    return read_info(ctx, f, &info);
+  };
+  int it = 0;
+  for (;;) {
+    ++it;
+    HIP_TRY(ctx, launch_laplace_terms((int)n, beta, x, d_y, g, sw, lik, rhs, s));
+    if ((rc = factor_B()) != MPCR_OK) return rc;
+    if ((rc = ensure_linv(ctx, f)) != MPCR_OK) return rc;
+    HIP_TRY(ctx, op.residual(nullptr, rhs, t, n, 1, s));               // t = -Sigma rhs
+    HIP_TRY(ctx, launch_scale((int)n, sw, t, -1.0, b.B, s));            // W^1/2 Sigma rhs
+    if ((rc = tile_solve(ctx, f, b, b.B, b.X, b.W)) != MPCR_OK) return rc;  // B^-1 (...)
+    HIP_TRY(ctx, launch_laplace_a((int)n, rhs, sw, b.X, a, s));          // a = rhs - W^1/2 B^-1 W^1/2 Sigma rhs
+    HIP_TRY(ctx, op.residual(nullptr, a, t, n, 1, s));                  // t = -Sigma a
+    HIP_TRY(ctx, launch_scale((int)n, ones, t, -1.0, xn, s));           // x_new = Sigma a
+    HIP_TRY(ctx, launch_step_diff((int)n, xn, x, d, s));                 // d = x_new - x, x = x_new
+    HIP_TRY(ctx, launch_col_dot((int)n, 1, d, d, n, partial, red, s));
+    double ss = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&ss, red, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (!std::isfinite(ss)) return set_err(ctx, MPCR_ERR_NOT_CONVERGED, "Newton iteration diverged");
+    if (ss / (double)n < tol) break;
+    if (it >= max_newton) return set_err(ctx, MPCR_ERR_NOT_CONVERGED, "Newton iteration reached max_newton");
+  }
+  // at the mode: W, B and log|B|; x^T Sigma^-1 x = a^T x since x = Sigma a
+  HIP_TRY(ctx, launch_laplace_terms((int)n, beta, x, d_y, g, sw, lik, rhs, s));
+  if ((rc = factor_B()) != MPCR_OK) return rc;
+  HIP_TRY(ctx, launch_logdet(f->view(), red, s));
+  HIP_TRY(ctx, launch_col_dot((int)n, 1, a, x, n, partial, red + 1, s));
+  HIP_TRY(ctx, launch_col_dot((int)n, 1, lik, ones, n, partial, red + 2, s));
+  double h[3];
+  HIP_TRY(ctx, hipMemcpyAsync(h, red, 24, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  *h_lpost = h[2] - 0.5 * h[1] - 0.5 * h[0];
+  if (h_iters) *h_iters = it;
+  return MPCR_OK;
+}
+}  // namespace
+
 // ===========================================================================
 // exported entry points
 // ===========================================================================
@@ -1201,7 +1276,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     ctx->ws_n = n;
   }
   auto ensure_factor = [&](const std::vector<uint8_t>& mm) -> int {
-    if (ctx->ws_factor && ctx->ws_nb == nb && ctx->ws_map == mm) return MPCR_OK;
+    if (ctx->ws_factor && ctx->ws_factor->n == n && ctx->ws_nb == nb && ctx->ws_map == mm) return MPCR_OK;
     free_factor(ctx->ws_factor);
     ctx->ws_factor = nullptr;
     ctx->ws_map.clear();
@@ -1478,6 +1553,69 @@ int mpcr_mle_fit(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d
   *h_nll_out = val[0];
   if (h_iters) *h_iters = it;
   if (h_evals) *h_evals = evals;
+  return MPCR_OK;
+}
+
+
+int mpcr_inla_posterior(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_y, double sigma2, double nu,
+                        double beta, const double* h_range, int nrange, double newton_tol, int max_newton,
+                        const mpcr_tilemap_t* map, double* h_lpost, double* h_posterior, int* h_newton_iters,
+                        double* d_mode_out) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs && d_y && h_range && h_lpost, "bad arguments");
+  CHECK_ARG(ctx, nu == 0.5 || nu == 1.5 || nu == 2.5, "nu must be 0.5, 1.5 or 2.5");
+  CHECK_ARG(ctx, sigma2 > 0 && std::isfinite(sigma2) && std::isfinite(beta) && newton_tol > 0 && max_newton >= 1,
+            "bad sigma2 / beta / Newton options");
+  CHECK_ARG(ctx, nrange >= 1, "need at least one range value");
+  for (int i = 0; i < nrange; ++i) CHECK_ARG(ctx, h_range[i] > 0 && std::isfinite(h_range[i]), "ranges must be > 0");
+  if (h_posterior) {
+    CHECK_ARG(ctx, nrange >= 3 && nrange % 2 == 1, "the Simpson posterior needs an odd number (>= 3) of ranges");
+    const double hstep = h_range[1] - h_range[0];
+    for (int i = 1; i < nrange; ++i)
+      CHECK_ARG(ctx, hstep > 0 && std::fabs(h_range[i] - h_range[i - 1] - hstep) <= 1e-9 * hstep,
+                "the Simpson posterior needs equally spaced increasing ranges");
+  }
+  std::vector<uint8_t> m;
+  int64_t nb = 256;
+  int rc;
+  if (map) {
+    if ((rc = check_map(ctx, n, map, m, nb)) != MPCR_OK) return rc;
+  } else {
+    const int64_t nt = (n + nb - 1) / nb;
+    m.assign(nt * nt, 255);
+    for (int64_t i = 0; i < nt; ++i)
+      for (int64_t j = 0; j <= i; ++j) m[i * nt + j] = F64;
+  }
+  DeviceGuard g(ctx->device);
+  double* vec = nullptr;
+  HIP_TRY(ctx, dmalloc(ctx->arena, &vec, (size_t)(10 * n + 8) * 8));
+  rc = MPCR_OK;
+  for (int i = 0; i < nrange && rc == MPCR_OK; ++i) {
+    mpcr_theta_t th{sigma2, h_range[i], nu, 0.0};
+    rc = laplace_one(ctx, n, nb, m, d_locs, d_y, th, beta, newton_tol, max_newton, vec, &h_lpost[i],
+                     h_newton_iters ? &h_newton_iters[i] : nullptr);
+    if (rc == MPCR_OK && d_mode_out && i == nrange - 1)
+      rc = hipMemcpyAsync(d_mode_out, vec, n * 8, hipMemcpyDeviceToDevice, ctx->stream) == hipSuccess
+               ? MPCR_OK
+               : set_err(ctx, MPCR_ERR_DEVICE, "mode copy failed");
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  dfree(ctx->arena, vec);
+  if (rc) return rc;
+  if (h_posterior) {
+    // the paper's normalisation: centre the log values, Simpson's rule over the grid
+    double mean = 0;
+    for (int i = 0; i < nrange; ++i) mean += h_lpost[i];
+    mean /= nrange;
+    const double hstep = h_range[1] - h_range[0];
+    double z = 0;
+    for (int i = 0; i < nrange; ++i) {
+      const double w = (i == 0 || i == nrange - 1) ? 1.0 : (i % 2 == 1 ? 4.0 : 2.0);
+      z += w * std::exp(h_lpost[i] - mean);
+    }
+    z *= hstep / 3.0;
+    for (int i = 0; i < nrange; ++i) h_posterior[i] = std::exp(h_lpost[i] - mean) / z;
+  }
   return MPCR_OK;
 }
 

@@ -291,6 +291,16 @@ hipError_t launch_loglik(int n, int nrhs, const double* logdet, const double* qu
 hipError_t launch_quad_refined(int n, int nrhs, const double* Z, const double* X, const double* R, int64_t ld,
                                double* partial, double* quad, hipStream_t s);
 
+// I + diag(w) Sigma diag(w) into the tile store (Sigma from the sites)
+hipError_t launch_tiles_from_weighted_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
+                                                 const double* w, hipStream_t s);
+// Laplace approximation, Bernoulli-logit observations: element-wise steps
+hipError_t launch_laplace_terms(int n, double beta, const double* x, const double* y, double* g, double* s,
+                                double* lik, double* b, hipStream_t st);
+hipError_t launch_scale(int n, const double* s, const double* u, double sign, double* out, hipStream_t st);
+hipError_t launch_laplace_a(int n, const double* b, const double* s, const double* v, double* a, hipStream_t st);
+hipError_t launch_step_diff(int n, const double* xnew, double* xold, double* d, hipStream_t st);
+
 // Allocation-free ordering: the sort keys live in a static device array of
 // MORTON_NOALLOC_MAX_KEYS entries (8 MiB per GPU).
 constexpr int MORTON_NOALLOC_MAX_KEYS = 1 << 20;

@@ -41,17 +41,20 @@ __device__ __forceinline__ void tri_unpack(int t, int& i, int& j) {
 // the tile (consecutive across threads, so stores are coalesced) and walks the
 // 16 columns; a column's coordinates are the same for the whole workgroup.
 // The tile's format is resolved once per workgroup.
+// MODE 0: Sigma from the sites; 1: from a dense FP64 lower triangle;
+// 2: I + diag(w) Sigma diag(w) from the sites and per-site weights w.
 template <int MODE, int F>
 __device__ __forceinline__ void fill_slab(void* tile, int sc, int ti, int tj, int c0, int nb, int n,
                                           const double* src, int64_t lds, double s2, double range, int nuc,
-                                          double nugget, double* sig) {
+                                          double nugget, double* sig, const double* wsc) {
   for (int r = threadIdx.x; r < nb; r += blockDim.x) {
     const int R = ti * nb + r;
     const bool rin = R < n;
-    double xr = 0.0, yr = 0.0;
-    if (MODE == 0 && rin) {
+    double xr = 0.0, yr = 0.0, wr = 0.0;
+    if (MODE != 1 && rin) {
       xr = src[R];
       yr = src[n + R];
+      if (MODE == 2) wr = wsc[R];
     }
 #pragma unroll 4
     for (int cc = 0; cc < 16; ++cc) {
@@ -59,12 +62,13 @@ __device__ __forceinline__ void fill_slab(void* tile, int sc, int ti, int tj, in
       double v;
       if (!rin || C >= n) {
         v = (R == C) ? 1.0 : 0.0;
-      } else if (MODE == 0) {
+      } else if (MODE != 1) {
         const double dx = xr - src[C];
         const double dy = yr - src[n + C];
         const double d = sqrt(dx * dx + dy * dy);
         v = s2 * matern_corr(d / range, nuc);
         if (R == C) v += nugget;
+        if (MODE == 2) v = wr * v * wsc[C] + (R == C ? 1.0 : 0.0);
       } else {
         const int hi = R > C ? R : C, lo = R > C ? C : R;
         v = src[(int64_t)lo * lds + hi];
@@ -76,9 +80,10 @@ __device__ __forceinline__ void fill_slab(void* tile, int sc, int ti, int tj, in
   }
 }
 
-template <int MODE>  // 0: from covariance, 1: from dense FP64 lower triangle
+template <int MODE>  // 0: from covariance, 1: from dense FP64 lower triangle, 2: I + W Sigma W
 __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* src, int64_t lds, double s2,
-                                                   double range, int nuc, double nugget, double* sig64) {
+                                                   double range, int nuc, double nugget, double* sig64,
+                                                   const double* wsc) {
   int ti, tj;
   tri_unpack(blockIdx.x, ti, tj);
   const int nb = tv.nb, n = tv.n;
@@ -88,24 +93,31 @@ __global__ __launch_bounds__(256) void k_fill_tiles(TileView tv, const double* s
   const int c0 = blockIdx.y * 16;
   double* sig = sig64 ? sig64 + (int64_t)blockIdx.x * nb * nb : nullptr;  // FP64 copy, packed tile order
   switch (f) {
-    case F64: fill_slab<MODE, F64>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
-    case F32: fill_slab<MODE, F32>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
-    case F16: fill_slab<MODE, F16>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
-    case BF16: fill_slab<MODE, BF16>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
-    default: fill_slab<MODE, F8>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig); break;
+    case F64: fill_slab<MODE, F64>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig, wsc); break;
+    case F32: fill_slab<MODE, F32>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig, wsc); break;
+    case F16: fill_slab<MODE, F16>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig, wsc); break;
+    case BF16: fill_slab<MODE, BF16>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig, wsc); break;
+    default: fill_slab<MODE, F8>(tile, sc, ti, tj, c0, nb, n, src, lds, s2, range, nuc, nugget, sig, wsc); break;
   }
 }
 
 hipError_t launch_tiles_from_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
                                         hipStream_t s, double* sig64) {
   dim3 grid(tv.nt * (tv.nt + 1) / 2, tv.nb / 16);
-  k_fill_tiles<0><<<grid, 256, 0, s>>>(tv, locs, 0, th.sigma2, th.range, nu_code(th.nu), th.nugget, sig64);
+  k_fill_tiles<0><<<grid, 256, 0, s>>>(tv, locs, 0, th.sigma2, th.range, nu_code(th.nu), th.nugget, sig64, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles_from_weighted_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
+                                                 const double* w, hipStream_t s) {
+  dim3 grid(tv.nt * (tv.nt + 1) / 2, tv.nb / 16);
+  k_fill_tiles<2><<<grid, 256, 0, s>>>(tv, locs, 0, th.sigma2, th.range, nu_code(th.nu), th.nugget, nullptr, w);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles_from_dense(const TileView& tv, const double* A, int64_t lda, hipStream_t s) {
   dim3 grid(tv.nt * (tv.nt + 1) / 2, tv.nb / 16);
-  k_fill_tiles<1><<<grid, 256, 0, s>>>(tv, A, lda, 0, 1, 0, 0, nullptr);
+  k_fill_tiles<1><<<grid, 256, 0, s>>>(tv, A, lda, 0, 1, 0, 0, nullptr, nullptr);
   return hipGetLastError();
 }
 

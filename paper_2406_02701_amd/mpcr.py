@@ -98,6 +98,8 @@ _SIGS = {
     "mpcr_loglik_map": (_i32, [_vp, _P(_i64), _P(C.c_uint8), _i64]),
     "mpcr_mle_fit": (_i32, [_vp, _i64, _vp, _vp, _d, _d, _P(mpcr_tilemap_t), _P(mpcr_refine_opts_t), _P(_d), _i32,
                             _d, _P(_d), _P(_d), _P(_i32), _P(_i32)]),
+    "mpcr_inla_posterior": (_i32, [_vp, _i64, _vp, _vp, _d, _d, _d, _P(_d), _i32, _d, _i32, _P(mpcr_tilemap_t),
+                                   _P(_d), _P(_d), _P(_i32), _vp]),
     "mpcr_convert": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mpcr_serve_create": (_i32, [_i32, C.c_size_t, _i32, _P(mpcr_serve_opts_t), _P(_vp)]),
     "mpcr_serve_destroy": (_i32, [_vp]),
