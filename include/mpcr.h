@@ -349,6 +349,27 @@ int mpcr_inla_posterior(mpcr_ctx* ctx, int64_t n, const double* d_locs, const do
                         const mpcr_tilemap_t* map, double* h_lpost, double* h_posterior, int* h_newton_iters,
                         double* d_mode_out);
 
+/* Metropolis-adjusted Langevin sampler (the paper's "Metropolis-Hastings
+ * Algorithm in High Dimensions" section) for the target N(0, Sigma) with
+ * Sigma the Matern covariance `target` at the sites d_locs (n x 2), the
+ * preconditioner M the Matern covariance `precond` and step h.  From the state
+ * z (d_z0, n), iteration t proposes
+ *   z' = z - (h/2) M Sigma^-1 z + L eps_t,   L L^T = h M  (lower tile factor),
+ * eps_t the t-th column of d_eps (n x iters, device), and accepts it when
+ *   h_unif[t] < exp(min(0, log pi(z') - log pi(z) + log q(z | z') - log q(z' | z)))
+ * with log pi(x) = -x^T Sigma^-1 x / 2 and log q(a | b) = -(a - s(b))^T
+ * (h M)^-1 (a - s(b)) / 2, s(b) = b - (h/2) M Sigma^-1 b.  Sigma and h M are
+ * factored once (tile map `map` for both, NULL = all FP64 with nb 256); the
+ * products Sigma^-1 x and (h M)^-1 quadratic forms are tile solves, M v is
+ * generated from the sites.  The random numbers are inputs, so a run is
+ * reproducible.  Outputs: d_z_out (n) the final state; d_trace (n x iters,
+ * may be NULL) every state; h_accepted and h_log_ratio (iters, may be NULL)
+ * the decisions and the log acceptance ratios. */
+int mpcr_mala_run(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* target,
+                  const mpcr_theta_t* precond, double h, const double* d_z0, int iters, const double* d_eps,
+                  const double* h_unif, const mpcr_tilemap_t* map, double* d_z_out, double* d_trace,
+                  int* h_accepted, double* h_log_ratio);
+
 /* ---- matrix product ----------------------------------------------------------- */
 
 /* Round an FP64 matrix (m x n, column-major, lds) once to format `prec`

@@ -1619,6 +1619,147 @@ int mpcr_inla_posterior(mpcr_ctx* ctx, int64_t n, const double* d_locs, const do
   return MPCR_OK;
 }
 
+int mpcr_mala_run(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* target,
+                  const mpcr_theta_t* precond, double h, const double* d_z0, int iters, const double* d_eps,
+                  const double* h_unif, const mpcr_tilemap_t* map, double* d_z_out, double* d_trace,
+                  int* h_accepted, double* h_log_ratio) {
+  CHECK_ARG(ctx, ctx != nullptr, "NULL context");
+  int rc = check_theta(ctx, target);
+  if (rc) return rc;
+  if ((rc = check_theta(ctx, precond)) != MPCR_OK) return rc;
+  CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs && d_z0 && d_z_out && iters >= 0, "bad arguments");
+  CHECK_ARG(ctx, iters == 0 || (d_eps && h_unif), "need the noise and the uniforms");
+  CHECK_ARG(ctx, h > 0 && std::isfinite(h), "need h > 0");
+  std::vector<uint8_t> m;
+  int64_t nb = 256;
+  if (map) {
+    if ((rc = check_map(ctx, n, map, m, nb)) != MPCR_OK) return rc;
+  } else {
+    const int64_t nt = (n + nb - 1) / nb;
+    m.assign(nt * nt, 255);
+    for (int64_t i = 0; i < nt; ++i)
+      for (int64_t j = 0; j <= i; ++j) m[i * nt + j] = F64;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  // factors of the target covariance Sigma and of h M (M the preconditioner)
+  mpcr_factor *fs = nullptr, *fm = nullptr;
+  double* vec = nullptr;
+  auto release = [&] {
+    (void)hipStreamSynchronize(s);
+    free_factor(fs);
+    free_factor(fm);
+    dfree(ctx->arena, vec);
+  };
+  const mpcr_theta_t thm{h * precond->sigma2, precond->range, precond->nu, h * precond->nugget};
+  auto factor = [&](mpcr_factor** f, const mpcr_theta_t& th) -> int {
+    int r = make_factor(ctx, n, nb, m, f);
+    if (r) return r;
+    HIP_TRY(ctx, hipMemsetAsync((*f)->d_info, 0, sizeof(int), s));
+    if ((*f)->has_f8) {
+      HIP_TRY(ctx, launch_covariance_tile_amax((int)n, (int)nb, d_locs, th, (*f)->d_tamax, s));
+      HIP_TRY(ctx, launch_fp8_scales((*f)->view(), (*f)->d_tamax, s));
+    }
+    HIP_TRY(ctx, launch_tiles_from_covariance((*f)->view(), d_locs, th, s));
+    if ((r = run_factorisation(ctx, *f)) != MPCR_OK) return r;
+    int64_t info = 0;
+    if ((r = read_info(ctx, *f, &info)) != MPCR_OK) return r;
+    return ensure_linv(ctx, *f);
+  };
+  if ((rc = factor(&fs, *target)) != MPCR_OK || (rc = factor(&fm, thm)) != MPCR_OK) {
+    release();
+    return rc;
+  }
+  const int64_t N = fs->N;
+  SolveBufs b;
+  if ((rc = carve(ctx, N, 1, n, b)) != MPCR_OK) {
+    release();
+    return rc;
+  }
+  // state and work vectors (padded order N, tails zero)
+  if (dmalloc(ctx->arena, &vec, (size_t)(10 * N + 8) * 8) != hipSuccess) {
+    release();
+    return set_err(ctx, MPCR_ERR_NOMEM, "device allocation failed");
+  }
+  double *z = vec, *gz = vec + N, *stz = vec + 2 * N, *zp = vec + 3 * N, *gzp = vec + 4 * N, *stzp = vec + 5 * N,
+         *t = vec + 6 * N, *dq = vec + 7 * N, *le = vec + 8 * N, *ones = vec + 9 * N, *red = vec + 10 * N;
+  SigmaOp opm;  // products with M (unscaled) from the sites
+  opm.locs = d_locs;
+  opm.th = *precond;
+  opm.n = (int)n;
+  auto fail = [&](hipError_t e) {
+    release();
+    return set_err(ctx, e == hipErrorOutOfMemory ? MPCR_ERR_NOMEM : MPCR_ERR_DEVICE, "%s", hipGetErrorString(e));
+  };
+  hipError_t e = launch_fill(vec, 10 * N, 0.0, s);
+  if (e == hipSuccess) e = launch_fill(ones, n, 1.0, s);
+  if (e == hipSuccess) e = launch_copy_cols((int)n, 1, d_z0, n, z, N, s);
+  if (e != hipSuccess) return fail(e);
+  // grad-related quantities of a state x: g = Sigma^-1 x, st = x - (h/2) M g
+  auto drift = [&](const double* x, double* gx, double* stx) -> int {
+    int r = tile_solve(ctx, fs, b, x, gx, b.W);
+    if (r) return r;
+    hipError_t e2 = opm.residual(nullptr, gx, t, N, 1, s);  // t = -M g
+    if (e2 == hipSuccess) e2 = launch_axpby((int)n, x, 0.5 * h, t, stx, s);
+    return e2 == hipSuccess ? MPCR_OK : set_err(ctx, MPCR_ERR_DEVICE, "%s", hipGetErrorString(e2));
+  };
+  // -(1/2) v^T (h M)^-1 v = -(1/2) ||L_hM^-1 v||^2 into red[slot]
+  auto qform = [&](const double* v, int slot) -> int {
+    int r = tile_solve(ctx, fm, b, v, b.X, b.W, false);
+    if (r) return r;
+    hipError_t e2 = launch_col_dot((int)n, 1, b.W, b.W, N, b.partial, red + slot, s);
+    return e2 == hipSuccess ? MPCR_OK : set_err(ctx, MPCR_ERR_DEVICE, "%s", hipGetErrorString(e2));
+  };
+  if ((rc = drift(z, gz, stz)) != MPCR_OK) {
+    release();
+    return rc;
+  }
+  for (int it = 0; it < iters; ++it) {
+    // proposal z' = z - (h/2) M Sigma^-1 z + L_hM eps
+    e = launch_copy_cols((int)n, 1, d_eps + (int64_t)it * n, n, dq, N, s);
+    if (e == hipSuccess) e = launch_trmv_lower(fm->view(), dq, le, s);
+    if (e == hipSuccess) e = launch_axpby((int)n, stz, 1.0, le, zp, s);
+    if (e != hipSuccess) return fail(e);
+    if ((rc = drift(zp, gzp, stzp)) != MPCR_OK) {
+      release();
+      return rc;
+    }
+    // log target ratio and the two proposal densities
+    e = launch_col_dot((int)n, 1, zp, gzp, N, b.partial, red + 0, s);
+    if (e == hipSuccess) e = launch_col_dot((int)n, 1, z, gz, N, b.partial, red + 1, s);
+    if (e == hipSuccess) e = launch_axpby((int)n, z, -1.0, stzp, dq, s);  // z - st(z')
+    if (e != hipSuccess) return fail(e);
+    if ((rc = qform(dq, 2)) != MPCR_OK) {
+      release();
+      return rc;
+    }
+    if ((e = launch_axpby((int)n, zp, -1.0, stz, dq, s)) != hipSuccess) return fail(e);  // z' - st(z)
+    if ((rc = qform(dq, 3)) != MPCR_OK) {
+      release();
+      return rc;
+    }
+    double hv[4];
+    if ((e = hipMemcpyAsync(hv, red, 32, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return fail(e);
+    const double logr = -0.5 * hv[0] + 0.5 * hv[1] - 0.5 * hv[2] + 0.5 * hv[3];
+    const bool acc = h_unif[it] < std::exp(std::min(0.0, logr));
+    if (h_log_ratio) h_log_ratio[it] = logr;
+    if (h_accepted) h_accepted[it] = acc ? 1 : 0;
+    if (acc) {
+      std::swap(z, zp);
+      std::swap(gz, gzp);
+      std::swap(stz, stzp);
+    }
+    if (d_trace && (e = launch_copy_cols((int)n, 1, z, N, d_trace + (int64_t)it * n, n, s)) != hipSuccess)
+      return fail(e);
+  }
+  e = launch_copy_cols((int)n, 1, z, N, d_z_out, n, s);
+  if (e != hipSuccess) return fail(e);
+  release();
+  return MPCR_OK;
+}
+
 int mpcr_loglik_map(const mpcr_ctx* ctx, int64_t* h_nt, uint8_t* h_map_out, int64_t capacity) {
   if (!ctx || !h_nt) return MPCR_ERR_ARG;
   if (!ctx->ws_factor || ctx->ws_map.empty()) return MPCR_ERR_ARG;

@@ -301,6 +301,10 @@ hipError_t launch_scale(int n, const double* s, const double* u, double sign, do
 hipError_t launch_laplace_a(int n, const double* b, const double* s, const double* v, double* a, hipStream_t st);
 hipError_t launch_step_diff(int n, const double* xnew, double* xold, double* d, hipStream_t st);
 
+// y = L x with the lower tile factor (MALA proposal noise); out = a + alpha b
+hipError_t launch_trmv_lower(const TileView& tv, const double* x, double* y, hipStream_t s);
+hipError_t launch_axpby(int n, const double* a, double alpha, const double* b, double* out, hipStream_t s);
+
 // Allocation-free ordering: the sort keys live in a static device array of
 // MORTON_NOALLOC_MAX_KEYS entries (8 MiB per GPU).
 constexpr int MORTON_NOALLOC_MAX_KEYS = 1 << 20;

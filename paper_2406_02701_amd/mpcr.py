@@ -100,6 +100,8 @@ _SIGS = {
                             _d, _P(_d), _P(_d), _P(_i32), _P(_i32)]),
     "mpcr_inla_posterior": (_i32, [_vp, _i64, _vp, _vp, _d, _d, _d, _P(_d), _i32, _d, _i32, _P(mpcr_tilemap_t),
                                    _P(_d), _P(_d), _P(_i32), _vp]),
+    "mpcr_mala_run": (_i32, [_vp, _i64, _vp, _P(mpcr_theta_t), _P(mpcr_theta_t), _d, _vp, _i32, _vp, _P(_d),
+                             _P(mpcr_tilemap_t), _vp, _vp, _P(_i32), _P(_d)]),
     "mpcr_convert": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "mpcr_serve_create": (_i32, [_i32, C.c_size_t, _i32, _P(mpcr_serve_opts_t), _P(_vp)]),
     "mpcr_serve_destroy": (_i32, [_vp]),
