@@ -90,7 +90,8 @@ __device__ void tile_mfma(const void* M, int nb, int r0, const double* V, int64_
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
   const int kw = nb / SW;
-  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+  // one 16-column chunk of right-hand sides per workgroup row of the grid
+  for (int c0 = blockIdx.y * RHS_CHUNK; c0 < nrhs && c0 < (int)(blockIdx.y + 1) * RHS_CHUNK; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     mfma_span<F, TRANS>(M, nb, r0 + c, w * kw, (w + 1) * kw, c < nc ? V + (int64_t)(c0 + c) * vsc : nullptr, vsk,
@@ -176,7 +177,7 @@ __device__ void tile_mfma4(const void* M, int nb, int r0, const double* V, int64
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int q = lane >> 4, c = lane & 15;
   const int kw = nb / SW4;
-  for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+  for (int c0 = blockIdx.y * RHS_CHUNK; c0 < nrhs && c0 < (int)(blockIdx.y + 1) * RHS_CHUNK; c0 += RHS_CHUNK) {
     const int nc = (nrhs - c0) < RHS_CHUNK ? (nrhs - c0) : RHS_CHUNK;
     d4 acc[4];
 #pragma unroll
@@ -279,10 +280,11 @@ __global__ __launch_bounds__(64 * SW4) void k_bwd_update4(TileView tv, int k, do
 }
 
 constexpr int WIDE_MIN_TILES = 16;  // update launches over at least this many tiles use 64-row workgroups
+static unsigned nchunk(int nrhs) { return (unsigned)((nrhs + RHS_CHUNK - 1) / RHS_CHUNK); }
 
 hipError_t launch_fwd_diag(const TileView& tv, const double* Linv, int k, double* R, double* W, int64_t ld,
                            int nrhs, double* stage, hipStream_t s) {
-  k_fwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info, stage);
+  k_fwd_diag<<<dim3(tv.nb / 16, nchunk(nrhs)), STHREADS, 0, s>>>(tv.nb, Linv, k, R, W, ld, nrhs, tv.info, stage);
   return hipGetLastError();
 }
 hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double* stage, int64_t ld, int nrhs,
@@ -290,23 +292,23 @@ hipError_t launch_fwd_update(const TileView& tv, int k, double* R, const double*
   int nt = tv.nt - k - 1;
   if (nt <= 0) return hipSuccess;
   if (nt >= WIDE_MIN_TILES)
-    k_fwd_update4<<<nt * (tv.nb / 64), 64 * SW4, 0, s>>>(tv, k, R, stage, ld, nrhs);
+    k_fwd_update4<<<dim3(nt * (tv.nb / 64), nchunk(nrhs)), 64 * SW4, 0, s>>>(tv, k, R, stage, ld, nrhs);
   else
-    k_fwd_update<<<nt * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, R, stage, ld, nrhs);
+    k_fwd_update<<<dim3(nt * (tv.nb / 16), nchunk(nrhs)), STHREADS, 0, s>>>(tv, k, R, stage, ld, nrhs);
   return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const TileView& tv, const double* Linv, int k, double* V, double* X, int64_t ld,
                            int nrhs, double* stage, hipStream_t s) {
-  k_bwd_diag<<<tv.nb / 16, STHREADS, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info, stage);
+  k_bwd_diag<<<dim3(tv.nb / 16, nchunk(nrhs)), STHREADS, 0, s>>>(tv.nb, Linv, k, V, X, ld, nrhs, tv.info, stage);
   return hipGetLastError();
 }
 hipError_t launch_bwd_update(const TileView& tv, int k, double* V, const double* stage, int64_t ld, int nrhs,
                              hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (k >= WIDE_MIN_TILES)
-    k_bwd_update4<<<k * (tv.nb / 64), 64 * SW4, 0, s>>>(tv, k, V, stage, ld, nrhs);
+    k_bwd_update4<<<dim3(k * (tv.nb / 64), nchunk(nrhs)), 64 * SW4, 0, s>>>(tv, k, V, stage, ld, nrhs);
   else
-    k_bwd_update<<<k * (tv.nb / 16), STHREADS, 0, s>>>(tv, k, V, stage, ld, nrhs);
+    k_bwd_update<<<dim3(k * (tv.nb / 16), nchunk(nrhs)), STHREADS, 0, s>>>(tv, k, V, stage, ld, nrhs);
   return hipGetLastError();
 }
 
