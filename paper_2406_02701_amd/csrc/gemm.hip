@@ -308,6 +308,146 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(int64_t M, int64_t N, int64_t
       }
 }
 
+// ---------------------------------------------------------------------------
+// Large 16-bit products (m, n multiples of 256, k a multiple of 64): one
+// workgroup of eight waves (two per SIMD) computes a 256 x 256 block of C;
+// wave (wm, wn), wm < 2, wn < 4, owns rows 128 wm .. +127 and columns
+// 64 wn .. +63 as 8 x 4 tiles of 16 x 16 (measured: 8 waves of 128 x 64 run
+// 1.27x faster than 4 waves of 128 x 128, whose accumulators fill every
+// accumulation register and force copies).  Stages of 64 k: both operands' 256 rows of 128
+// bytes are moved global -> registers -> LDS (rows padded to 144 bytes, so
+// the 16-byte fragment reads of 16 consecutive rows hit disjoint banks),
+// double-buffered with one barrier per stage; the next stage's global loads
+// are in flight during the current stage's MFMAs.  The MFMA takes the B
+// fragment as its first operand, so a lane's four results are four columns of
+// one row of C: for each register the 16 lanes of a group store 16
+// consecutive rows (64 contiguous bytes) of a column.
+// ---------------------------------------------------------------------------
+constexpr int BG = 256;  // block of C per workgroup of the large kernel
+
+template <int P, int WN>  // WN waves along n (2: 128 x 128 per wave, 4: 128 x 64 per wave)
+__global__ __launch_bounds__(128 * WN) void k_gemm_lowp_big(int64_t M, int64_t N, int64_t K, double alpha,
+                                                            const void* ATv, int64_t ldat, const void* Bv,
+                                                            int64_t ldb, double beta, void* Cv, int64_t ldc,
+                                                            int cprec) {
+  static_assert(P == BF16 || P == F16, "16-bit formats");
+  constexpr int NT = 128 * WN;           // threads
+  constexpr int TN = BG / WN / 16;       // 16-column tiles per wave
+  constexpr int RPL = NT / 8;            // rows per load instruction
+  constexpr int NV = BG / RPL;           // 16-byte vectors per thread and operand
+  constexpr int ES = 2, BK = 64, ROWB = BK * ES, LDR = ROWB + 16;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][BG * LDR];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BG * LDR];
+  const uint8_t* AT = (const uint8_t*)ATv;
+  const uint8_t* B = (const uint8_t*)Bv;
+  // XCD-aware order, grouped 8 block rows high (blocks in flight on one XCD share panels)
+  const int gm = gridDim.x, gn = gridDim.y;
+  const int lb = xcd_remap(blockIdx.y * gm + blockIdx.x, gm * gn);
+  constexpr int GROUP = 8;
+  const int group = lb / (GROUP * gn), first = group * GROUP;
+  const int rows = (gm - first) < GROUP ? (gm - first) : GROUP;
+  const int bi = first + (lb % (GROUP * gn)) % rows, bj = (lb % (GROUP * gn)) / rows;
+  const int64_t r0 = (int64_t)bi * BG, c0 = (int64_t)bj * BG;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int g16 = lane & 15, q = lane >> 4;
+
+  // loader: thread t moves 16-byte vector (row t / 8 + RPL v, chunk t % 8), v < NV,
+  // of one operand at a time (A during the first half of a stage, B during the
+  // second).  The last stage reloads itself (no branch around the staging, so
+  // the staged vectors stay in registers); its copies are never read.
+  const int lrow = tid >> 3, lchunk = tid & 7;
+  const uint8_t* ga = AT + ((r0 + lrow) * ldat) * ES + lchunk * 16;
+  const uint8_t* gb = B + ((c0 + lrow) * ldb) * ES + lchunk * 16;
+  const int64_t stepa = RPL * ldat * ES, stepb = RPL * ldb * ES;
+  const int soff = lrow * LDR + lchunk * 16;
+
+  f4 acc[8][TN];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+  uint4 g0, g1, g2, g3, g4, g5, g6, g7;  // g4 .. g7 unused with 8 waves
+#define MPCR_GLOAD(G, STEP, KB)                                                                       \
+  g0 = *(const uint4*)(G + 0 * STEP + KB); g1 = *(const uint4*)(G + 1 * STEP + KB);                  \
+  g2 = *(const uint4*)(G + 2 * STEP + KB); g3 = *(const uint4*)(G + 3 * STEP + KB);                  \
+  if constexpr (NV == 8) {                                                                           \
+    g4 = *(const uint4*)(G + 4 * STEP + KB); g5 = *(const uint4*)(G + 5 * STEP + KB);                \
+    g6 = *(const uint4*)(G + 6 * STEP + KB); g7 = *(const uint4*)(G + 7 * STEP + KB);                \
+  }
+#define MPCR_SSTORE(S)                                                                                \
+  *(uint4*)&S[soff + 0 * RPL * LDR] = g0; *(uint4*)&S[soff + 1 * RPL * LDR] = g1;                    \
+  *(uint4*)&S[soff + 2 * RPL * LDR] = g2; *(uint4*)&S[soff + 3 * RPL * LDR] = g3;                    \
+  if constexpr (NV == 8) {                                                                           \
+    *(uint4*)&S[soff + 4 * RPL * LDR] = g4; *(uint4*)&S[soff + 5 * RPL * LDR] = g5;                  \
+    *(uint4*)&S[soff + 6 * RPL * LDR] = g6; *(uint4*)&S[soff + 7 * RPL * LDR] = g7;                  \
+  }
+  MPCR_GLOAD(ga, stepa, 0)
+  MPCR_SSTORE(As[0])
+  MPCR_GLOAD(gb, stepb, 0)
+  MPCR_SSTORE(Bs[0])
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    const int64_t kn = (k0 + BK < K ? k0 + BK : k0) * ES;  // the next stage (the last one reloads itself)
+    MPCR_GLOAD(ga, stepa, kn)
+    const uint8_t* Ab = &As[cur][(wm * 128 + g16) * LDR];
+    const uint8_t* Bb = &Bs[cur][(wn * TN * 16 + g16) * LDR];
+#pragma unroll
+    for (int k32 = 0; k32 < BK; k32 += 32) {
+      if (k32 == 32) {  // the next stage's A is in registers: store it, fetch its B
+        MPCR_SSTORE(As[cur ^ 1])
+        MPCR_GLOAD(gb, stepb, kn)
+      }
+      const int kb = (k32 + 8 * q) * ES;
+      u16x8 bv[TN];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = *(const u16x8*)(Bb + b * 16 * LDR + kb);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const u16x8 av = *(const u16x8*)(Ab + a * 16 * LDR + kb);
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          if constexpr (P == BF16)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bv[b]),
+                                                                 __builtin_bit_cast(bf16x8, av), acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, bv[b]),
+                                                                __builtin_bit_cast(f16x8, av), acc[a][b], 0, 0, 0);
+        }
+      }
+    }
+    MPCR_SSTORE(Bs[cur ^ 1])
+    __syncthreads();
+    cur ^= 1;
+  }
+#undef MPCR_GLOAD
+#undef MPCR_SSTORE
+
+  // lane (g16, q), register r of tile (a, b): C[r0 + 128 wm + 16 a + g16][c0 + 16 TN wn + 16 b + 4 q + r]
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = r0 + wm * 128 + a * 16 + g16;
+        const int64_t Cc = c0 + wn * TN * 16 + b * 16 + 4 * q + r;
+        const int64_t idx = Cc * ldc + R;
+        double v = alpha * (double)acc[a][b][r];
+        if (cprec == F64) {
+          double* Cp = (double*)Cv;
+          if (beta != 0.0) v += beta * Cp[idx];
+          Cp[idx] = v;
+        } else {
+          float* Cp = (float*)Cv;
+          if (beta != 0.0) v += beta * (double)Cp[idx];
+          Cp[idx] = (float)v;
+        }
+      }
+}
+
 // Packs a rows x cols operand into a k-contiguous array: out[r * ldo + c] =
 // element (r, c), read from in[c * ldi + r] (TR) or in[r * ldi + c] (!TR).
 // 64 x 64 pieces go through LDS so that both the reads and the writes are
@@ -347,6 +487,14 @@ hipError_t launch_gemm_lowp(int prec, int64_t m, int64_t n, int64_t k, double al
                             const int8_t* sA, int64_t mbA, int sa_kmajor, const void* B, int64_t ldb,
                             const int8_t* sB, int64_t mbB, int sb_kmajor, double beta, void* C, int64_t ldc, int cprec,
                             hipStream_t s) {
+  // whole 256 x 256 blocks and 64-wide k stages with 16-byte aligned rows: the large kernel
+  if ((prec == BF16 || prec == F16) && m % BG == 0 && n % BG == 0 && k % 64 == 0 && k > 0 && (ldat * 2) % 16 == 0 &&
+      (ldb * 2) % 16 == 0 && (uintptr_t)AT % 16 == 0 && (uintptr_t)B % 16 == 0) {
+    dim3 g2((unsigned)(m / BG), (unsigned)(n / BG));
+    if (prec == BF16) k_gemm_lowp_big<BF16, 4><<<g2, 512, 0, s>>>(m, n, k, alpha, AT, ldat, B, ldb, beta, C, ldc, cprec);
+    else k_gemm_lowp_big<F16, 4><<<g2, 512, 0, s>>>(m, n, k, alpha, AT, ldat, B, ldb, beta, C, ldc, cprec);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((m + GB - 1) / GB), (unsigned)((n + GB - 1) / GB));
   switch (prec) {
     case BF16: k_gemm_lowp<BF16><<<grid, 256, 0, s>>>(m, n, k, alpha, AT, ldat, sA, mbA, B, ldb, sB, mbB, sa_kmajor, sb_kmajor, beta, C, ldc, cprec); break;

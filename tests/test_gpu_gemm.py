@@ -122,6 +122,25 @@ def test_gemm_matches_emulation(g, fmt, tA, tB):
     assert err <= 4 * math.sqrt(k) * u_acc(fmt), err
 
 
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("tA,tB", [(False, False), (True, False)])
+def test_gemm_large_blocks_match_emulation(g, fmt, tA, tB):
+    """m, n multiples of 256 and k of 64: the 256 x 256-block kernel (several
+    blocks and k stages; alpha, beta)."""
+    gu, ctx = g
+    m, n, k = 512, 768, 1024
+    A = synth.uniform_matrix(k if tA else m, m if tA else k, 110)
+    B = synth.uniform_matrix(n if tB else k, k if tB else n, 111)
+    C0r = ff.round_to(synth.uniform_matrix(m, n, 112), "fp32")
+    got = run_gemm(gu, ctx, fmt, A, B, tA, tB, alpha=0.75, beta=-0.5, C0=C0r)
+    ref = og.gemm_emulated(A, B, fmt, transA=tA, transB=tB, alpha=0.75, beta=-0.5, C=C0r, c_fmt="fp32")
+    err = og.rel_frobenius(got, ref)
+    assert err <= 4 * math.sqrt(k) * u_acc(fmt), err
+    A = synth.integer_matrix(m, k, 113)
+    B = synth.integer_matrix(k, n, 114)
+    assert np.array_equal(run_gemm(gu, ctx, fmt, A, B, False, False), A @ B)
+
+
 @pytest.mark.parametrize("fmt", FMTS)
 def test_gemm_integer_inputs_exact(g, fmt):
     gu, ctx = g
