@@ -352,10 +352,10 @@ __global__ __launch_bounds__(128 * WN) void k_gemm_lowp_big(int64_t M, int64_t N
   const int wm = wave & 1, wn = wave >> 1;
   const int g16 = lane & 15, q = lane >> 4;
 
-  // loader: thread t moves 16-byte vector (row t / 8 + RPL v, chunk t % 8), v < NV,
-  // of one operand at a time (A during the first half of a stage, B during the
-  // second).  The last stage reloads itself (no branch around the staging, so
-  // the staged vectors stay in registers); its copies are never read.
+  // loader: thread t moves 16-byte vectors (row t / 8 + RPL v, chunk t % 8),
+  // v < NV, of both operands.  The last stage reloads itself (no branch around
+  // the staging, so the staged vectors stay in registers); its copies are
+  // never read.
   const int lrow = tid >> 3, lchunk = tid & 7;
   const uint8_t* ga = AT + ((r0 + lrow) * ldat) * ES + lchunk * 16;
   const uint8_t* gb = B + ((c0 + lrow) * ldb) * ES + lchunk * 16;
@@ -368,59 +368,63 @@ __global__ __launch_bounds__(128 * WN) void k_gemm_lowp_big(int64_t M, int64_t N
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f4{0, 0, 0, 0};
 
-  uint4 g0, g1, g2, g3, g4, g5, g6, g7;  // g4 .. g7 unused with 8 waves
-#define MPCR_GLOAD(G, STEP, KB)                                                                       \
-  g0 = *(const uint4*)(G + 0 * STEP + KB); g1 = *(const uint4*)(G + 1 * STEP + KB);                  \
-  g2 = *(const uint4*)(G + 2 * STEP + KB); g3 = *(const uint4*)(G + 3 * STEP + KB);                  \
-  if constexpr (NV == 8) {                                                                           \
-    g4 = *(const uint4*)(G + 4 * STEP + KB); g5 = *(const uint4*)(G + 5 * STEP + KB);                \
-    g6 = *(const uint4*)(G + 6 * STEP + KB); g7 = *(const uint4*)(G + 7 * STEP + KB);                \
-  }
-#define MPCR_SSTORE(S)                                                                                \
-  *(uint4*)&S[soff + 0 * RPL * LDR] = g0; *(uint4*)&S[soff + 1 * RPL * LDR] = g1;                    \
-  *(uint4*)&S[soff + 2 * RPL * LDR] = g2; *(uint4*)&S[soff + 3 * RPL * LDR] = g3;                    \
-  if constexpr (NV == 8) {                                                                           \
-    *(uint4*)&S[soff + 4 * RPL * LDR] = g4; *(uint4*)&S[soff + 5 * RPL * LDR] = g5;                  \
-    *(uint4*)&S[soff + 6 * RPL * LDR] = g6; *(uint4*)&S[soff + 7 * RPL * LDR] = g7;                  \
-  }
-  MPCR_GLOAD(ga, stepa, 0)
-  MPCR_SSTORE(As[0])
-  MPCR_GLOAD(gb, stepb, 0)
-  MPCR_SSTORE(Bs[0])
+  static_assert(NV == 4, "four 16-byte vectors per thread and operand");
+  uint4 ga0, ga1, ga2, ga3, gb0, gb1, gb2, gb3;
+#define MPCR_GLOAD(KB)                                                                                \
+  ga0 = *(const uint4*)(ga + 0 * stepa + KB); ga1 = *(const uint4*)(ga + 1 * stepa + KB);            \
+  ga2 = *(const uint4*)(ga + 2 * stepa + KB); ga3 = *(const uint4*)(ga + 3 * stepa + KB);            \
+  gb0 = *(const uint4*)(gb + 0 * stepb + KB); gb1 = *(const uint4*)(gb + 1 * stepb + KB);            \
+  gb2 = *(const uint4*)(gb + 2 * stepb + KB); gb3 = *(const uint4*)(gb + 3 * stepb + KB);
+#define MPCR_SSTORE(BUF)                                                                              \
+  *(uint4*)&As[BUF][soff + 0 * RPL * LDR] = ga0; *(uint4*)&As[BUF][soff + 1 * RPL * LDR] = ga1;      \
+  *(uint4*)&As[BUF][soff + 2 * RPL * LDR] = ga2; *(uint4*)&As[BUF][soff + 3 * RPL * LDR] = ga3;      \
+  *(uint4*)&Bs[BUF][soff + 0 * RPL * LDR] = gb0; *(uint4*)&Bs[BUF][soff + 1 * RPL * LDR] = gb1;      \
+  *(uint4*)&Bs[BUF][soff + 2 * RPL * LDR] = gb2; *(uint4*)&Bs[BUF][soff + 3 * RPL * LDR] = gb3;
+
+  // fragments of one 32-wide k step: A rows 16 a + g16, B columns 16 b + g16,
+  // k values 8 q .. 8 q + 7 of the step
+  u16x8 fa0[8], fb0[TN], fa1[8], fb1[TN];
+  auto frag = [&](int buf, int k32, u16x8* fa, u16x8* fb) {
+    const int kb = (k32 + 8 * q) * ES;
+    const uint8_t* Ab = &As[buf][(wm * 128 + g16) * LDR + kb];
+    const uint8_t* Bb = &Bs[buf][(wn * TN * 16 + g16) * LDR + kb];
+#pragma unroll
+    for (int b = 0; b < TN; ++b) fb[b] = *(const u16x8*)(Bb + b * 16 * LDR);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) fa[a] = *(const u16x8*)(Ab + a * 16 * LDR);
+  };
+  auto mma = [&](const u16x8* fa, const u16x8* fb) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        if constexpr (P == BF16)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, fb[b]),
+                                                               __builtin_bit_cast(bf16x8, fa[a]), acc[a][b], 0, 0, 0);
+        else
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, fb[b]),
+                                                              __builtin_bit_cast(f16x8, fa[a]), acc[a][b], 0, 0, 0);
+      }
+  };
+  MPCR_GLOAD(0)
+  MPCR_SSTORE(0)
   __syncthreads();
   int cur = 0;
+  frag(0, 0, fa0, fb0);
+  // per stage: the next stage's A and B are requested at its start and stored
+  // to the other LDS buffer at its end; the second step's fragments are read
+  // while the first step's MFMAs run; after the barrier the next stage's first
+  // fragments are read
   for (int64_t k0 = 0; k0 < K; k0 += BK) {
     const int64_t kn = (k0 + BK < K ? k0 + BK : k0) * ES;  // the next stage (the last one reloads itself)
-    MPCR_GLOAD(ga, stepa, kn)
-    const uint8_t* Ab = &As[cur][(wm * 128 + g16) * LDR];
-    const uint8_t* Bb = &Bs[cur][(wn * TN * 16 + g16) * LDR];
-#pragma unroll
-    for (int k32 = 0; k32 < BK; k32 += 32) {
-      if (k32 == 32) {  // the next stage's A is in registers: store it, fetch its B
-        MPCR_SSTORE(As[cur ^ 1])
-        MPCR_GLOAD(gb, stepb, kn)
-      }
-      const int kb = (k32 + 8 * q) * ES;
-      u16x8 bv[TN];
-#pragma unroll
-      for (int b = 0; b < TN; ++b) bv[b] = *(const u16x8*)(Bb + b * 16 * LDR + kb);
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const u16x8 av = *(const u16x8*)(Ab + a * 16 * LDR + kb);
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          if constexpr (P == BF16)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bv[b]),
-                                                                 __builtin_bit_cast(bf16x8, av), acc[a][b], 0, 0, 0);
-          else
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, bv[b]),
-                                                                __builtin_bit_cast(f16x8, av), acc[a][b], 0, 0, 0);
-        }
-      }
-    }
-    MPCR_SSTORE(Bs[cur ^ 1])
+    MPCR_GLOAD(kn)
+    frag(cur, 32, fa1, fb1);
+    mma(fa0, fb0);
+    mma(fa1, fb1);
+    MPCR_SSTORE(cur ^ 1)
     __syncthreads();
     cur ^= 1;
+    frag(cur, 0, fa0, fb0);
   }
 #undef MPCR_GLOAD
 #undef MPCR_SSTORE
