@@ -452,6 +452,129 @@ __global__ __launch_bounds__(128 * WN) void k_gemm_lowp_big(int64_t M, int64_t N
       }
 }
 
+// ---------------------------------------------------------------------------
+// Large FP8 products (m, n multiples of 256, k a multiple of 128): the same
+// 256 x 256 blocking, eight waves of 128 x 64 and operand staging as the
+// 16-bit kernel, with stages of 128 k = one block of the power-of-two
+// scaling.  Each 16 x 16 tile of a stage is one gfx950 block-scaled MFMA
+// (v_mfma_scale_f32_16x16x128_f8f6f4, E4M3 operands): its E8M0 scales
+// 2^(127 - e) undo the operands' block exponents inside the instruction
+// (exact powers of two), so the stages accumulate straight into the FP32
+// results.  A lane supplies 32 consecutive k of one row or column; the same
+// lane-to-k assignment for both operands makes the sum correct for any
+// internal order of the 128 products.
+// ---------------------------------------------------------------------------
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(512) void k_gemm_fp8_big(int64_t M, int64_t N, int64_t K, double alpha,
+                                                     const void* ATv, int64_t ldat, const int8_t* sA, int64_t mbA,
+                                                     int sa_kmajor, const void* Bv, int64_t ldb, const int8_t* sB,
+                                                     int64_t mbB, int sb_kmajor, double beta, void* Cv,
+                                                     int64_t ldc, int cprec) {
+  constexpr int WN = 4, NT = 512, TN = 4;  // waves along n, threads, 16-column tiles per wave
+  constexpr int BK = 128, ROWB = BK, LDR = ROWB + 16;
+  constexpr int RPL = NT / 8;              // rows per load instruction
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][BG * LDR];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BG * LDR];
+  const uint8_t* AT = (const uint8_t*)ATv;
+  const uint8_t* B = (const uint8_t*)Bv;
+  const int gm = gridDim.x, gn = gridDim.y;
+  const int lb = xcd_remap(blockIdx.y * gm + blockIdx.x, gm * gn);
+  constexpr int GROUP = 8;
+  const int group = lb / (GROUP * gn), first = group * GROUP;
+  const int rows = (gm - first) < GROUP ? (gm - first) : GROUP;
+  const int bi = first + (lb % (GROUP * gn)) % rows, bj = (lb % (GROUP * gn)) / rows;
+  const int64_t r0 = (int64_t)bi * BG, c0 = (int64_t)bj * BG;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int g16 = lane & 15, q = lane >> 4;
+  // the scale blocks of this wave's rows and columns
+  const int64_t ib = (r0 + 128 * wm) / 128, jb = (c0 + 64 * wn) / 128;
+
+  const int lrow = tid >> 3, lchunk = tid & 7;
+  const uint8_t* ga = AT + (r0 + lrow) * ldat + lchunk * 16;
+  const uint8_t* gb = B + (c0 + lrow) * ldb + lchunk * 16;
+  const int64_t stepa = RPL * ldat, stepb = RPL * ldb;
+  const int soff = lrow * LDR + lchunk * 16;
+
+  f4 acc[8][TN];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+  uint4 ga0, ga1, ga2, ga3, gb0, gb1, gb2, gb3;
+#define MPCR_GLOAD(KB)                                                                                \
+  ga0 = *(const uint4*)(ga + 0 * stepa + KB); ga1 = *(const uint4*)(ga + 1 * stepa + KB);            \
+  ga2 = *(const uint4*)(ga + 2 * stepa + KB); ga3 = *(const uint4*)(ga + 3 * stepa + KB);            \
+  gb0 = *(const uint4*)(gb + 0 * stepb + KB); gb1 = *(const uint4*)(gb + 1 * stepb + KB);            \
+  gb2 = *(const uint4*)(gb + 2 * stepb + KB); gb3 = *(const uint4*)(gb + 3 * stepb + KB);
+#define MPCR_SSTORE(BUF)                                                                              \
+  *(uint4*)&As[BUF][soff + 0 * RPL * LDR] = ga0; *(uint4*)&As[BUF][soff + 1 * RPL * LDR] = ga1;      \
+  *(uint4*)&As[BUF][soff + 2 * RPL * LDR] = ga2; *(uint4*)&As[BUF][soff + 3 * RPL * LDR] = ga3;      \
+  *(uint4*)&Bs[BUF][soff + 0 * RPL * LDR] = gb0; *(uint4*)&Bs[BUF][soff + 1 * RPL * LDR] = gb1;      \
+  *(uint4*)&Bs[BUF][soff + 2 * RPL * LDR] = gb2; *(uint4*)&Bs[BUF][soff + 3 * RPL * LDR] = gb3;
+
+  auto frag = [&](const uint8_t* p) {  // 32 consecutive bytes
+    const uint4 lo = *(const uint4*)p, hi = *(const uint4*)(p + 16);
+    return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+  };
+  MPCR_GLOAD(0)
+  MPCR_SSTORE(0)
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    const int64_t kn = k0 + BK < K ? k0 + BK : k0;  // the next stage (the last one reloads itself)
+    MPCR_GLOAD(kn)
+    const int64_t kb = k0 / 128;
+    const int ea = sa_kmajor ? sA[ib * mbA + kb] : sA[kb * mbA + ib];
+    const int eb = sb_kmajor ? sB[kb * mbB + jb] : sB[jb * mbB + kb];
+    // E8M0 scale bytes 2^(127 - e) (exponents below -127 are outside E8M0's range: clamped)
+    const int sca = 127 - ea < 0 ? 0 : (127 - ea > 254 ? 254 : 127 - ea);
+    const int scb = 127 - eb < 0 ? 0 : (127 - eb > 254 ? 254 : 127 - eb);
+    const uint8_t* Ab = &As[cur][(wm * 128 + g16) * LDR + 32 * q];
+    const uint8_t* Bb = &Bs[cur][(wn * TN * 16 + g16) * LDR + 32 * q];
+    i32x8 fb[TN];
+#pragma unroll
+    for (int b = 0; b < TN; ++b) fb[b] = frag(Bb + b * 16 * LDR);
+    i32x8 fa = frag(Ab);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const i32x8 fan = frag(Ab + ((a + 1) & 7) * 16 * LDR);  // the next row block's fragment
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fb[b], fa, acc[a][b], 0, 0, 0, scb, 0, sca);
+      fa = fan;
+    }
+    MPCR_SSTORE(cur ^ 1)
+    __syncthreads();
+    cur ^= 1;
+  }
+#undef MPCR_GLOAD
+#undef MPCR_SSTORE
+
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = r0 + wm * 128 + a * 16 + g16;
+        const int64_t Cc = c0 + wn * TN * 16 + b * 16 + 4 * q + r;
+        const int64_t idx = Cc * ldc + R;
+        double v = alpha * (double)acc[a][b][r];
+        if (cprec == F64) {
+          double* Cp = (double*)Cv;
+          if (beta != 0.0) v += beta * Cp[idx];
+          Cp[idx] = v;
+        } else {
+          float* Cp = (float*)Cv;
+          if (beta != 0.0) v += beta * (double)Cp[idx];
+          Cp[idx] = (float)v;
+        }
+      }
+}
+
 // Packs a rows x cols operand into a k-contiguous array: out[r * ldo + c] =
 // element (r, c), read from in[c * ldi + r] (TR) or in[r * ldi + c] (!TR).
 // 64 x 64 pieces go through LDS so that both the reads and the writes are
@@ -497,6 +620,13 @@ hipError_t launch_gemm_lowp(int prec, int64_t m, int64_t n, int64_t k, double al
     dim3 g2((unsigned)(m / BG), (unsigned)(n / BG));
     if (prec == BF16) k_gemm_lowp_big<BF16, 4><<<g2, 512, 0, s>>>(m, n, k, alpha, AT, ldat, B, ldb, beta, C, ldc, cprec);
     else k_gemm_lowp_big<F16, 4><<<g2, 512, 0, s>>>(m, n, k, alpha, AT, ldat, B, ldb, beta, C, ldc, cprec);
+    return hipGetLastError();
+  }
+  if (prec == F8 && m % BG == 0 && n % BG == 0 && k % 128 == 0 && k >= 128 && ldat % 16 == 0 && ldb % 16 == 0 &&
+      (uintptr_t)AT % 16 == 0 && (uintptr_t)B % 16 == 0) {
+    dim3 g2((unsigned)(m / BG), (unsigned)(n / BG));
+    k_gemm_fp8_big<<<g2, 512, 0, s>>>(m, n, k, alpha, AT, ldat, sA, mbA, sa_kmajor, B, ldb, sB, mbB, sb_kmajor, beta,
+                                      C, ldc, cprec);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((m + GB - 1) / GB), (unsigned)((n + GB - 1) / GB));

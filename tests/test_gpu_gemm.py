@@ -122,11 +122,11 @@ def test_gemm_matches_emulation(g, fmt, tA, tB):
     assert err <= 4 * math.sqrt(k) * u_acc(fmt), err
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8_e4m3"])
 @pytest.mark.parametrize("tA,tB", [(False, False), (True, False)])
 def test_gemm_large_blocks_match_emulation(g, fmt, tA, tB):
-    """m, n multiples of 256 and k of 64: the 256 x 256-block kernel (several
-    blocks and k stages; alpha, beta)."""
+    """m, n multiples of 256 and k of 64 (FP8: 128): the 256 x 256-block
+    kernels (several blocks and k stages; alpha, beta)."""
     gu, ctx = g
     m, n, k = 512, 768, 1024
     A = synth.uniform_matrix(k if tA else m, m if tA else k, 110)
@@ -135,7 +135,13 @@ def test_gemm_large_blocks_match_emulation(g, fmt, tA, tB):
     got = run_gemm(gu, ctx, fmt, A, B, tA, tB, alpha=0.75, beta=-0.5, C0=C0r)
     ref = og.gemm_emulated(A, B, fmt, transA=tA, transB=tB, alpha=0.75, beta=-0.5, C=C0r, c_fmt="fp32")
     err = og.rel_frobenius(got, ref)
-    assert err <= 4 * math.sqrt(k) * u_acc(fmt), err
+    print(f"{fmt} large blocks tA={tA}: rel-F vs emulation {err:.3e}", flush=True)
+    if fmt == "fp8_e4m3":
+        Ar = og.input_rounded(A.T if tA else A, fmt)
+        Br = og.input_rounded(B.T if tB else B, fmt)
+        assert np.all(np.abs(got - ref) <= 0.75 * fp8_bound(Ar, Br) + 2.0 ** -24 * np.abs(ref) * 2)
+    else:
+        assert err <= 4 * math.sqrt(k) * u_acc(fmt), err
     A = synth.integer_matrix(m, k, 113)
     B = synth.integer_matrix(k, n, 114)
     assert np.array_equal(run_gemm(gu, ctx, fmt, A, B, False, False), A @ B)
@@ -267,3 +273,22 @@ def test_mfma_accumulation_models(g, sign):
           flush=True)
     assert rel.max() > 0            # the small products really are cut
     assert hits["zero"] or hits["floor"]
+
+
+def test_fp8_block_scaled_mfma_accumulation(g):
+    """The large FP8 kernel (block-scaled 16x16x128 MFMA) on the structured
+    sums (one dominant product, many small ones; 256 x 256 x 128): its error
+    is within the group-truncation bound used for the FP8 gates (printed
+    beside the exact sums)."""
+    gu, ctx = g
+    k = 128
+    A, t = _structured(k, 1.0)
+    A = np.vstack([A, np.zeros((256 - A.shape[0], k))])
+    B = np.ones((k, 256))
+    got = run_gemm(gu, ctx, "fp8_e4m3", A, B, False, False)
+    exact = A @ B
+    Ar = og.input_rounded(A, "fp8_e4m3")
+    assert np.array_equal(Ar, A)
+    rel = np.max(np.abs(got[:22] - exact[:22]), axis=1) / exact[:22, 0]
+    print("block-scaled FP8 MFMA: relative error per row", [f"{v:.2e}" for v in rel], flush=True)
+    assert np.all(np.abs(got - exact) <= fp8_bound(Ar, B) + 2.0 ** -24 * np.abs(exact))
