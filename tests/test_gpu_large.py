@@ -177,11 +177,12 @@ def test_n32768_fp64_path_matches_oracle_golden(g):
 def test_n32768_guarded_mixed_path_matches_oracle_golden(g):
     """The band map breaks down in the oracle's tile step; the norm-guarded map
     is the oracle's, bit for bit; the mixed path refines every quadratic form
-    to the FP64 one (eta <= 1e-13: 1e-9 relative at this conditioning), and its
-    log-determinant lies within the emulated mixed factor's shift from the
-    FP64 log-determinant of the emulated value (the FP32-accumulated updates
-    perturb the factor about as much as the tile roundings the emulation
-    models)."""
+    to the FP64 one (eta <= 1e-13: 1e-9 relative at this conditioning).  The
+    log-determinant is not refinable: the emulated mixed factor (tile
+    roundings, exact accumulation) moves it by d_emu from the FP64 value; the
+    GPU's FP32 tiles also accumulate their 512-term updates in FP32 (about
+    sqrt(512) u32 per update where the emulation has u32), so its shift is
+    gated at 10 |d_emu|, and both shifts at 1e-6 of the log-determinant."""
     from paper_2406_02701_amd import mpcr
     gu, ctx = g
     gold = _gold32768()
@@ -203,4 +204,5 @@ def test_n32768_guarded_mixed_path_matches_oracle_golden(g):
     ld_emu, ld64 = gold["guarded"]["logdet"], gold["fp64"]["logdet"]
     print(f"n32768 mixed: logdet {d.logdet!r} emulated {ld_emu!r} fp64 {ld64!r}; "
           f"l vs fp64 {np.max(np.abs(ll - np.array(gold['fp64']['loglik'])) / np.abs(ll)):.2e}", flush=True)
-    assert abs(d.logdet - ld_emu) <= abs(ld_emu - ld64)
+    assert abs(d.logdet - ld64) <= 10 * abs(ld_emu - ld64)
+    assert max(abs(d.logdet - ld64), abs(ld_emu - ld64)) <= 1e-6 * abs(ld64)
