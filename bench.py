@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--no-gemm", action="store_true", help="skip the multi-format GEMM sweep")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="run only the multi-format GEMM sweep (for counter collection) and print its results")
     ap.add_argument("--no-other", action="store_true", help="skip the 1024- and 65536-site workloads")
     ap.add_argument("--no-n65536", action="store_true", help="skip the 65536-site workload")
     ap.add_argument("--guard-n65536", type=float, default=1e-4,
@@ -395,6 +397,9 @@ def main():
     torch.cuda.set_device(0)
     lib = Lib(torch)
     mp = lib.m
+    if args.gemm_only:
+        print(json.dumps({"gemm_sweep_8192": gemm_sweep(lib, torch, args.steps)}), flush=True)
+        return
     w = dict(synth.WORKLOADS["mixed_n32768"])
     if args.n:
         w["n"] = args.n

@@ -26,20 +26,25 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int GB = 128;  // block of C per workgroup
 
+// FP64 uses 8 waves of 64 x 32 (more waves per CU hide the staging of the
+// slow FP64 MFMA better than more work per wave), FP32 4 waves of 64 x 64;
+// both stage 16 k per chunk, double-buffered with one barrier per chunk (the
+// shapes of the factorisation's tile-update loop).
 template <int P> struct GTraits;
-template <> struct GTraits<F64> { using S = double; static constexpr int BK = 16; };
-template <> struct GTraits<F32> { using S = float; static constexpr int BK = 32; };
+template <> struct GTraits<F64> { using S = double; static constexpr int BK = 16, NW = 8, WPE = 2; };
+template <> struct GTraits<F32> { using S = float; static constexpr int BK = 16, NW = 4, WPE = 2; };
 
 // FP64 / FP32 path: operands staged k-major ([BK][GB + pad]) through LDS.
 template <int P>
-__global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
-                                              const void* Av, int64_t lda, const void* Bv, int64_t ldb, double beta,
-                                              void* Cv, int64_t ldc, int cprec) {
+__global__ __launch_bounds__(GTraits<P>::NW * 64) __attribute__((amdgpu_waves_per_eu(GTraits<P>::WPE))) void
+k_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const void* Av, int64_t lda,
+       const void* Bv, int64_t ldb, double beta, void* Cv, int64_t ldc, int cprec) {
   using S = typename GTraits<P>::S;
-  constexpr int BK = GTraits<P>::BK;
+  constexpr int BK = GTraits<P>::BK, NW = GTraits<P>::NW, NT = NW * 64;
+  constexpr int WM = 2, WN = NW / WM, TM = GB / WM, TN = GB / WN, FM = TM / 16, FN = TN / 16;
   constexpr int PADK = 16;  // rows k, k+1 (FP64) or k .. k+3 (FP32) of a fragment on disjoint banks
-  __shared__ __attribute__((aligned(16))) S As[BK][GB + PADK];
-  __shared__ __attribute__((aligned(16))) S Bs[BK][GB + PADK];
+  __shared__ __attribute__((aligned(16))) S As[2][BK][GB + PADK];
+  __shared__ __attribute__((aligned(16))) S Bs[2][BK][GB + PADK];
 
   const S* A = (const S*)Av;
   const S* B = (const S*)Bv;
@@ -53,16 +58,44 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
   const int bi = first + (lb % (GROUP * gn)) % rows, bj = (lb % (GROUP * gn)) / rows;
   const int64_t r0 = (int64_t)bi * GB, c0 = (int64_t)bj * GB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WM, wn = wave / WM;
 
-  constexpr int PER = GB * BK / 256;  // elements per thread per operand
+  constexpr int PER = GB * BK / NT;  // elements per thread per operand
+  constexpr int V = 16 / sizeof(S);  // elements per 16-byte vector
+  constexpr int PV = PER / V;        // vectors per thread per operand
   S ra[PER], rb[PER];
-  // element e of a 128 x BK slab: index order chosen so that consecutive threads
-  // read consecutive addresses of the stored matrix
+  // Whole blocks with 16-byte aligned columns move 16-byte vectors (V
+  // consecutive elements of the stored matrix: rows of a column, or k values
+  // of a transposed operand's column); other blocks move single elements with
+  // bounds checks.  Consecutive threads read consecutive addresses.
+  const bool vec = (r0 + GB <= M) && (c0 + GB <= N) && (K % BK == 0) && ((lda * (int64_t)sizeof(S)) % 16 == 0) &&
+                   ((ldb * (int64_t)sizeof(S)) % 16 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+  // vector v of a thread: (row-or-column index, k index) of its first element
+  auto avec = [&](int v, int& r, int& kk) {
+    const int e = tid + NT * v;
+    if (!transA) { r = (e % (GB / V)) * V; kk = e / (GB / V); } else { kk = (e % (BK / V)) * V; r = e / (BK / V); }
+  };
+  auto bvec = [&](int v, int& c, int& kb) {
+    const int e = tid + NT * v;
+    if (transB) { c = (e % (GB / V)) * V; kb = e / (GB / V); } else { kb = (e % (BK / V)) * V; c = e / (BK / V); }
+  };
   auto gload = [&](int64_t k0) {
+    if (vec) {
+#pragma unroll
+      for (int v = 0; v < PV; ++v) {
+        int r, kk, c, kb;
+        avec(v, r, kk);
+        bvec(v, c, kb);
+        const S* pa = A + (transA ? (r0 + r) * lda + k0 + kk : (k0 + kk) * lda + r0 + r);
+        const S* pb = B + (transB ? (k0 + kb) * ldb + c0 + c : (c0 + c) * ldb + k0 + kb);
+        *(uint4*)&ra[V * v] = *(const uint4*)pa;
+        *(uint4*)&rb[V * v] = *(const uint4*)pb;
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       int r, kk;
       if (!transA) { r = e % GB; kk = e / GB; } else { kk = e % BK; r = e / BK; }
       const int64_t gr = r0 + r, gk = k0 + kk;
@@ -73,62 +106,80 @@ __global__ __launch_bounds__(256) void k_gemm(int transA, int transB, int64_t M,
       rb[q] = (gc < N && gkb < K) ? B[transB ? gkb * ldb + gc : gc * ldb + gkb] : (S)0;
     }
   };
-  auto sstore = [&]() {
+  auto sstore = [&](int buf) {
+    if (vec) {
+#pragma unroll
+      for (int v = 0; v < PV; ++v) {
+        int r, kk, c, kb;
+        avec(v, r, kk);
+        bvec(v, c, kb);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          if (!transA) As[buf][kk][r + u] = ra[V * v + u]; else As[buf][kk + u][r] = ra[V * v + u];
+          if (transB) Bs[buf][kb][c + u] = rb[V * v + u]; else Bs[buf][kb + u][c] = rb[V * v + u];
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       int r, kk;
       if (!transA) { r = e % GB; kk = e / GB; } else { kk = e % BK; r = e / BK; }
-      As[kk][r] = ra[q];
+      As[buf][kk][r] = ra[q];
       int c, kb;
       if (transB) { c = e % GB; kb = e / GB; } else { kb = e % BK; c = e / BK; }
-      Bs[kb][c] = rb[q];
+      Bs[buf][kb][c] = rb[q];
     }
   };
 
   using Acc = typename std::conditional<P == F64, d4, f4>::type;
-  Acc acc[4][4];
+  Acc acc[FM][FN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  if (K > 0) gload(0);
+  if (K > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  int cur = 0;
   for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    sstore();
-    __syncthreads();
-    if (k0 + BK < K) gload(k0 + BK);
-    {
+    const bool more = k0 + BK < K;
+    if (more) gload(k0 + BK);
 #pragma unroll
-      for (int k4 = 0; k4 < BK; k4 += 4) {
-        S av[4], bv[4];
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      S av[FM], bv[FN];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[k4 + (lane >> 4)][wm * 64 + a * 16 + (lane & 15)];
+      for (int a = 0; a < FM; ++a) av[a] = As[cur][k4 + (lane >> 4)][wm * TM + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[k4 + (lane >> 4)][wn * 64 + b * 16 + (lane & 15)];
+      for (int b = 0; b < FN; ++b) bv[b] = Bs[cur][k4 + (lane >> 4)][wn * TN + b * 16 + (lane & 15)];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < FM; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            if constexpr (P == F64)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-            else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
-          }
-      }
+        for (int b = 0; b < FN; ++b) {
+          if constexpr (P == F64)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
     }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
   }
 
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = (P == F64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
-        const int64_t R = r0 + wm * 64 + a * 16 + row;
-        const int64_t C = c0 + wn * 64 + b * 16 + (lane & 15);
+        const int64_t R = r0 + wm * TM + a * 16 + row;
+        const int64_t C = c0 + wn * TN + b * 16 + (lane & 15);
         if (R >= M || C >= N) continue;
         const int64_t idx = C * ldc + R;
         double v = alpha * (double)acc[a][b][r];
@@ -644,8 +695,8 @@ hipError_t launch_gemm(int prec, int transA, int transB, int64_t m, int64_t n, i
                        hipStream_t s) {
   dim3 grid((unsigned)((m + GB - 1) / GB), (unsigned)((n + GB - 1) / GB));
   switch (prec) {
-    case F64: k_gemm<F64><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cprec); break;
-    case F32: k_gemm<F32><<<grid, 256, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cprec); break;
+    case F64: k_gemm<F64><<<grid, GTraits<F64>::NW * 64, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cprec); break;
+    case F32: k_gemm<F32><<<grid, GTraits<F32>::NW * 64, 0, s>>>(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cprec); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -122,20 +122,23 @@ def test_gemm_matches_emulation(g, fmt, tA, tB):
     assert err <= 4 * math.sqrt(k) * u_acc(fmt), err
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8_e4m3"])
-@pytest.mark.parametrize("tA,tB", [(False, False), (True, False)])
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("tA,tB", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_large_blocks_match_emulation(g, fmt, tA, tB):
-    """m, n multiples of 256 and k of 64 (FP8: 128): the 256 x 256-block
-    kernels (several blocks and k stages; alpha, beta)."""
+    """Whole blocks: m, n multiples of 256 and k of 64 (FP8: 128) take the
+    256 x 256-block kernels of the 16/8-bit formats and the 16-byte vector
+    loads of the FP64/FP32 kernel (several blocks and k stages; alpha, beta)."""
     gu, ctx = g
     m, n, k = 512, 768, 1024
     A = synth.uniform_matrix(k if tA else m, m if tA else k, 110)
     B = synth.uniform_matrix(n if tB else k, k if tB else n, 111)
     C0r = ff.round_to(synth.uniform_matrix(m, n, 112), "fp32")
+    cf = "fp64" if fmt == "fp64" else "fp32"
+    C0r = ff.round_to(C0r, cf)
     got = run_gemm(gu, ctx, fmt, A, B, tA, tB, alpha=0.75, beta=-0.5, C0=C0r)
-    ref = og.gemm_emulated(A, B, fmt, transA=tA, transB=tB, alpha=0.75, beta=-0.5, C=C0r, c_fmt="fp32")
+    ref = og.gemm_emulated(A, B, fmt, transA=tA, transB=tB, alpha=0.75, beta=-0.5, C=C0r, c_fmt=cf)
     err = og.rel_frobenius(got, ref)
-    print(f"{fmt} large blocks tA={tA}: rel-F vs emulation {err:.3e}", flush=True)
+    print(f"{fmt} large blocks tA={tA} tB={tB}: rel-F vs emulation {err:.3e}", flush=True)
     if fmt == "fp8_e4m3":
         Ar = og.input_rounded(A.T if tA else A, fmt)
         Br = og.input_rounded(B.T if tB else B, fmt)
