@@ -118,20 +118,21 @@ class Lib:
         return ms.value, n.value, fl.value
 
 
-def measured_traffic(kind):
-    """HBM bytes per launch of `kind` from the committed counter summary (scaled
-    FETCH_SIZE + WRITE_SIZE), or None once the kernel source has changed since
-    the counters were taken."""
+def measured_traffic(kind, guard):
+    """HBM bytes per launch of `kind` under the nugget guard `guard` from the
+    committed counter summary (scaled FETCH_SIZE + WRITE_SIZE), or None when
+    the summary has no such entry or the kernel source has changed since the
+    counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "tile_update_fp64_n32768_traffic.md")
-    if kind != "tile_update_fp64" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", "tile_update_n32768_traffic.md")
+    if not os.path.exists(path):
         return None
     rec = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith(("|", "#")))
     src = os.path.join(ROOT, "paper_2406_02701_amd", "csrc", "factor.hip")
-    if rec.get("kernel", "").strip() != kind or \
-            hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256", "").strip():
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256", "").strip():
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    v = rec.get(f"traffic_bytes_per_launch[{kind}@{guard:g}]")
+    return None if v is None else float(v)
 
 
 def banded(mp, n, nb, dmax, precs):
@@ -520,7 +521,7 @@ def main():
                 "launches": launches, "avg_launch_ms": avg_ms, "flops_per_launch": fl_per_launch}
 
     dom = max(range(NKIND), key=lambda k: kstats[k][0])
-    roofline = roof(kstats, dom, measured_traffic(KIND_NAME[dom]))
+    roofline = roof(kstats, dom, measured_traffic(KIND_NAME[dom], head_gmul) if n == 32768 else None)
     # the trailing updates share the GPU with the next-column and POTRF/TRSM
     # streams, so a launch's duration includes some sharing; the FP64 path's
     # figure is given beside it
