@@ -19,7 +19,7 @@ import numpy as np
 from . import covariance as cov
 from .dense import (NotPositiveDefinite, backward_substitution_transpose, forward_substitution,
                     gaussian_loglik, logdet_from_cholesky, loglik_fp64)
-from .refine import iterative_refinement, pcg, quad_refined
+from .refine import block_pcg, gmres_ir, iterative_refinement, pcg, quad_refined
 from .tiled import promote_after_breakdown, tile_cholesky_emulated
 
 
@@ -58,7 +58,7 @@ def loglik_mixed(locs, Z, sigma2, range_, nu, nugget, nb, tmap, tol=1e-9, max_it
     sig_inf = float(np.max(np.sum(np.abs(S), axis=1)))
     matvec = lambda X: S @ X
     precond = lambda R: backward_substitution_transpose(L, forward_substitution(L, R))
-    run = pcg if solver == "pcg" else iterative_refinement
+    run = {"pcg": pcg, "ir": iterative_refinement, "gmres": gmres_ir, "bpcg": block_pcg}[solver]
     res = run(matvec, Z2, precond, sig_inf, tol=tol, max_iter=max_iter)
     quad = quad_refined(Z2, res["X"], res["R"])
     rel = np.linalg.norm(res["R"], axis=0) / np.linalg.norm(Z2, axis=0)

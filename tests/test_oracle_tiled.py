@@ -98,7 +98,7 @@ def _matern_case(n, seed, a=0.1, nu=1.5, tau=1e-6):
     return locs, cov.covariance(locs, 1.0, a, nu, tau)
 
 
-@pytest.mark.parametrize("solver", ["pcg", "ir"])
+@pytest.mark.parametrize("solver", ["pcg", "ir", "gmres", "bpcg"])
 def test_refinement_reaches_fp64_solution(solver):
     n, nb = 384, 64
     locs, S = _matern_case(n, 41, a=0.05, nu=0.5, tau=1e-4)
@@ -107,7 +107,8 @@ def test_refinement_reaches_fp64_solution(solver):
     B = synth.normal_rhs(n, 3, 42)
     sig_inf = np.max(np.sum(np.abs(S), axis=1))
     pre = lambda R: dense.cholesky_solve(L, R)
-    run = refine.pcg if solver == "pcg" else refine.iterative_refinement
+    run = {"pcg": refine.pcg, "ir": refine.iterative_refinement, "gmres": refine.gmres_ir,
+           "bpcg": refine.block_pcg}[solver]
     out = run(lambda X: S @ X, B, pre, sig_inf, tol=1e-14, max_iter=50)
     assert out["converged"] and out["eta"] <= 1e-14
     Xd = dense.cholesky_solve(dense.cholesky_lower(S), B)
