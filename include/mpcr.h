@@ -97,7 +97,20 @@ typedef struct {
  *                (||r||_2/||b||_2 is reported as well)
  *   max_iter     iteration cap (0 = no refinement: x = M^{-1} b)
  *   solver       0 = preconditioned conjugate gradients, 1 = classical
- *                iterative refinement x <- x + M^{-1} r
+ *                iterative refinement x <- x + M^{-1} r, 2 = GMRES-based
+ *                iterative refinement (Carson and Higham, 2018): each
+ *                correction equation Sigma d = r is solved by GMRES (Saad and
+ *                Schultz, 1986; modified Gram-Schmidt, Givens rotations) on
+ *                M^{-1} Sigma d = M^{-1} r, at most gmres_m steps, until the
+ *                GMRES residual drops to gmres_inner_tol |M^{-1} r|; max_iter
+ *                counts the refinement steps.  3 = block PCG (O'Leary, 1980)
+ *                on groups of block_size consecutive columns:
+ *                alpha = (P^T Sigma P)^{-1} (Z^T R), beta = (Z^T R)_old^{-1}
+ *                (Z^T R)_new with Z = M^{-1} R; a group whose s x s system is
+ *                not numerically positive definite (a pivot of its unit-
+ *                diagonal scaling below 1e-12) finishes with PCG from its
+ *                current iterate.  diag->iters counts block iterations plus
+ *                any PCG iterations after such a breakdown.
  *   recompute    PCG recomputes the true residual every `recompute` steps
  *   residual     mpcr_gauss_loglik only: 0 = regenerate Sigma's entries from the
  *                sites for every residual (no extra memory); 1 = keep an FP64
@@ -119,7 +132,12 @@ typedef struct {
  *   direct_eta   all-FP64 map with max_iter = 0 (the paper's direct path):
  *                1 = also compute the backward error of the direct solve (one
  *                extra FP64 residual pass) into diag->eta / rel_resid2;
- *                0 = skip it.  opts == NULL behaves as 1 when diag != NULL. */
+ *                0 = skip it.  opts == NULL behaves as 1 when diag != NULL.
+ *   gmres_m      solver 2: GMRES steps per refinement step (0 = 20; at most 64)
+ *   gmres_inner_tol
+ *                solver 2: relative tolerance of each GMRES solve (0 = 1e-6)
+ *   block_size   solver 3: right-hand sides per block (0 = min(nrhs, 32);
+ *                at most 32) */
 typedef struct {
   double tol;
   int max_iter;
@@ -128,6 +146,9 @@ typedef struct {
   int residual;
   int promote_on_breakdown;
   int direct_eta;
+  int gmres_m;
+  double gmres_inner_tol;
+  int block_size;
 } mpcr_refine_opts_t;
 
 /* Diagnostics filled by mpcr_potrs / mpcr_gauss_loglik (host struct). */

@@ -28,7 +28,7 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INCLUDE}",
 ]
-SOURCES = ["tiles.hip", "factor.hip", "solve.hip", "order.hip", "gemm.hip", "laplace.hip", "mala.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["tiles.hip", "factor.hip", "solve.hip", "order.hip", "gemm.hip", "laplace.hip", "mala.hip", "krylov.hip", "api.cpp", "serve.cpp"]
 
 
 def _compile(src: str) -> str:

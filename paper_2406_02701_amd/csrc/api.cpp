@@ -92,6 +92,8 @@ struct mpcr_ctx {
   double* ws_locs = nullptr;      // n x 2 sorted sites
   double* ws_vec = nullptr;       // vector workspace
   int64_t ws_vec_bytes = 0;
+  void* ws_kry = nullptr;         // Krylov workspace of the GMRES and block PCG solvers
+  int64_t ws_kry_bytes = 0;
   uint8_t* ws_gemm = nullptr;     // packed 16/8-bit GEMM operands
   uint64_t* noalloc_keys = nullptr;  // device address of the static sort-key array on this device
   int64_t ws_gemm_bytes = 0;
@@ -613,7 +615,28 @@ struct SigmaOp {
   }
 };
 
-// Refined solve (PCG or IR) of Sigma X = B; B, X in b.B / b.X (padded N x nrhs).
+// Solver options common to mpcr_potrs and mpcr_gauss_loglik.
+bool refine_opts_ok(const mpcr_refine_opts_t& o) {
+  return o.tol > 0 && o.max_iter >= 0 && o.solver >= 0 && o.solver <= 3 && o.recompute >= 0 && o.gmres_m >= 0 &&
+         o.gmres_m <= 64 && o.gmres_inner_tol >= 0 && o.gmres_inner_tol < 1 && o.block_size >= 0 &&
+         o.block_size <= KRYLOV_MAX_BLOCK;
+}
+
+// Krylov workspace of at least `bytes` bytes (kept by the context).
+int krylov_ws(mpcr_ctx* ctx, int64_t bytes, char** out) {
+  if (ctx->ws_kry_bytes < bytes) {
+    dfree(ctx->arena, ctx->ws_kry);
+    ctx->ws_kry = nullptr;
+    ctx->ws_kry_bytes = 0;
+    HIP_TRY(ctx, dmalloc(ctx->arena, &ctx->ws_kry, (size_t)bytes));
+    ctx->ws_kry_bytes = bytes;
+  }
+  *out = (char*)ctx->ws_kry;
+  return MPCR_OK;
+}
+
+// Refined solve of Sigma X = B (PCG, IR, GMRES-IR or block PCG); B, X in
+// b.B / b.X (padded N x nrhs).
 int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const mpcr_refine_opts_t& o,
            mpcr_diag_t* diag, bool* converged_out) {
   hipStream_t s = ctx->stream;
@@ -656,8 +679,11 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
   if ((rc = push_active()) != MPCR_OK) return rc;
   int it = 0;
   bool r_true = true;  // R (and the fetched statistics) hold the true residual of the current X
-  if (o.solver == 0 && nact > 0) {
-    if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;  // z = M^{-1} r
+
+  // PCG from the current X, whose true residual is in R, on the active columns
+  auto pcg_loop = [&]() -> int {
+    int rc2;
+    if ((rc2 = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc2;  // z = M^{-1} r
     HIP_TRY(ctx, launch_copy_cols((int)b.N, nrhs, b.Z, ld, b.P, ld, s));
     HIP_TRY(ctx, launch_col_dot(n, nrhs, b.R, b.Z, ld, b.partial, rz, s));
     while (nact > 0 && it < o.max_iter) {
@@ -674,12 +700,12 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
         HIP_TRY(ctx, launch_axpy_cols(n, nrhs, alpha, -1.0, b.Q, b.R, ld, s)); // r -= alpha Sigma p
         r_true = false;
       }
-      if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+      if ((rc2 = fetch_stats(b.R)) != MPCR_OK) return rc2;
       bool any = false;
       for (int c = 0; c < nrhs; ++c) any |= act[c] && col_converged(c);
       if (any) {  // confirm with the true residual
         HIP_TRY(ctx, op.residual(b.B, b.X, b.W, ld, nrhs, s));
-        if ((rc = fetch_stats(b.W)) != MPCR_OK) return rc;
+        if ((rc2 = fetch_stats(b.W)) != MPCR_OK) return rc2;
         HIP_TRY(ctx, launch_copy_cols(n, nrhs, b.W, ld, b.R, ld, s));
         r_true = true;
         for (int c = 0; c < nrhs; ++c)
@@ -687,15 +713,20 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
             act[c] = 0;
             --nact;
           }
-        if ((rc = push_active()) != MPCR_OK) return rc;
+        if ((rc2 = push_active()) != MPCR_OK) return rc2;
       }
       if (nact == 0 || it >= o.max_iter) break;
-      if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;
+      if ((rc2 = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc2;
       HIP_TRY(ctx, launch_col_dot(n, nrhs, b.R, b.Z, ld, b.partial, rzn, s));
       HIP_TRY(ctx, launch_pcg_beta(nrhs, rzn, rz, b.active, beta, s));
       HIP_TRY(ctx, launch_xpby_cols(n, nrhs, b.Z, beta, b.P, ld, s));
     }
-  } else {
+    return MPCR_OK;
+  };
+
+  if (o.solver == 0 && nact > 0) {
+    if ((rc = pcg_loop()) != MPCR_OK) return rc;
+  } else if (o.solver == 1) {
     while (nact > 0 && it < o.max_iter) {
       ++it;
       if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;
@@ -711,6 +742,202 @@ int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const
           act[c] = 0;
           --nact;
         }
+    }
+  } else if (o.solver == 2 && nact > 0) {
+    // GMRES-IR: per refinement step, GMRES on M^-1 Sigma d = M^-1 r for every
+    // active column (one Hessenberg matrix per column), then x += d and the
+    // true residual.
+    const int m = o.gmres_m > 0 ? o.gmres_m : 20;
+    const double itol = o.gmres_inner_tol > 0 ? o.gmres_inner_tol : 1e-6;
+    const int64_t blk = ld * nrhs;
+    const int64_t need = 8 * ((int64_t)(m + 1) * blk + (int64_t)nrhs * ((m + 1) * m + 3 * (m + 1) + m + 8)) +
+                         4 * 3 * nrhs + 1024;
+    char* w;
+    if ((rc = krylov_ws(ctx, need, &w)) != MPCR_OK) return rc;
+    double* V = (double*)w;                                   // m + 1 blocks
+    double* H = V + (int64_t)(m + 1) * blk;                   // nrhs x (m+1) x m
+    double* cs = H + (int64_t)nrhs * (m + 1) * m;             // nrhs x (m+1)
+    double* sn = cs + (int64_t)nrhs * (m + 1);
+    double* g = sn + (int64_t)nrhs * (m + 1);
+    double* y = g + (int64_t)nrhs * (m + 1);                  // nrhs x m
+    double* bet = y + (int64_t)nrhs * m;                      // nrhs
+    double* inv = bet + nrhs;
+    double* dotv = inv + nrhs;
+    double* out = dotv + nrhs;                                // 2 nrhs
+    double* neg1 = out + 2 * nrhs;                            // nrhs
+    int* run_d = (int*)(neg1 + nrhs);
+    int* steps_d = run_d + nrhs;
+    HIP_TRY(ctx, launch_fill(neg1, nrhs, -1.0, s));
+    HIP_TRY(ctx, launch_fill(V, (int64_t)(m + 1) * blk, 0.0, s));
+    std::vector<double> hbeta(nrhs), hout(2 * nrhs);
+    std::vector<int> run(nrhs), steps(nrhs);
+    while (nact > 0 && it < o.max_iter) {
+      ++it;
+      if ((rc = push_active()) != MPCR_OK) return rc;
+      // v0 = M^-1 r / |M^-1 r|
+      if ((rc = tile_solve(ctx, f, b, b.R, V, b.W)) != MPCR_OK) return rc;
+      HIP_TRY(ctx, launch_col_dot(n, nrhs, V, V, ld, b.partial, dotv, s));
+      HIP_TRY(ctx, launch_gmres_start(nrhs, m, dotv, b.active, bet, g, inv, s));
+      HIP_TRY(ctx, launch_scale_cols(n, nrhs, inv, V, V, ld, s));
+      HIP_TRY(ctx, hipMemcpyAsync(hbeta.data(), bet, nrhs * 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      int nrun = 0;
+      for (int c = 0; c < nrhs; ++c) {
+        run[c] = act[c] && hbeta[c] > 0.0;
+        steps[c] = 0;
+        nrun += run[c];
+      }
+      int jmax = 0;
+      for (int j = 0; j < m && nrun > 0; ++j) {
+        HIP_TRY(ctx, hipMemcpyAsync(run_d, run.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+        const double* vj = V + (int64_t)j * blk;
+        // w = M^-1 Sigma v_j (the residual kernel gives -Sigma v_j)
+        HIP_TRY(ctx, op.residual(nullptr, vj, b.Q, ld, nrhs, s));
+        if ((rc = tile_solve(ctx, f, b, b.Q, b.Z, b.W)) != MPCR_OK) return rc;
+        HIP_TRY(ctx, launch_scale_cols(n, nrhs, neg1, b.Z, b.Z, ld, s));
+        // modified Gram-Schmidt against v_0 .. v_j
+        const int64_t hs = (int64_t)(m + 1) * m;
+        for (int i = 0; i <= j; ++i) {
+          double* hij = H + (int64_t)(m + 1) * j + i;
+          HIP_TRY(ctx, launch_col_dot_strided(n, nrhs, V + (int64_t)i * blk, b.Z, ld, b.partial, hij, hs, s));
+          HIP_TRY(ctx, launch_axpy_strided(n, nrhs, hij, hs, -1.0, V + (int64_t)i * blk, b.Z, ld, s));
+        }
+        HIP_TRY(ctx, launch_col_dot(n, nrhs, b.Z, b.Z, ld, b.partial, dotv, s));
+        HIP_TRY(ctx, launch_gmres_rotate(nrhs, m, j, dotv, run_d, H, cs, sn, g, out, s));
+        HIP_TRY(ctx, hipMemcpyAsync(hout.data(), out, 2 * nrhs * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        jmax = j + 1;
+        for (int c = 0; c < nrhs; ++c) {
+          if (!run[c]) continue;
+          steps[c] = j + 1;
+          if (hout[2 * c] <= itol * hbeta[c] || hout[2 * c + 1] == 0.0) {
+            run[c] = 0;
+            --nrun;
+          }
+        }
+        if (nrun == 0 || j + 1 == m) break;
+        // v_{j+1} = w / |w| for the columns that continue (0 for the others)
+        HIP_TRY(ctx, hipMemcpyAsync(run_d, run.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, launch_gmres_inv(nrhs, out, run_d, inv, s));
+        HIP_TRY(ctx, launch_scale_cols(n, nrhs, inv, b.Z, V + (int64_t)(j + 1) * blk, ld, s));
+      }
+      // x += V_k y, y from the rotated Hessenberg system
+      HIP_TRY(ctx, hipMemcpyAsync(steps_d, steps.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+      HIP_TRY(ctx, launch_gmres_backsolve(nrhs, m, H, g, steps_d, y, s));
+      for (int i = 0; i < jmax; ++i)
+        HIP_TRY(ctx, launch_axpy_strided(n, nrhs, y + i, m, 1.0, V + (int64_t)i * blk, b.X, ld, s));
+      HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+      if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+      for (int c = 0; c < nrhs; ++c)
+        if (act[c] && col_converged(c)) {
+          act[c] = 0;
+          --nact;
+        }
+    }
+    r_true = true;
+  } else if (o.solver == 3 && nact > 0) {
+    // block PCG on groups of bs consecutive columns, all groups in lockstep
+    const int bs = o.block_size > 0 ? std::min(o.block_size, nrhs) : std::min(nrhs, KRYLOV_MAX_BLOCK);
+    const int ng = (nrhs + bs - 1) / bs;
+    const int64_t sq = (int64_t)ng * bs * bs;
+    const int64_t need = 8 * 5 * sq + (int64_t)gram_partial_bytes(n, nrhs, bs) + 4 * 2 * ng + 1024;
+    char* w;
+    if ((rc = krylov_ws(ctx, need, &w)) != MPCR_OK) return rc;
+    double* PQ = (double*)w;   // P^T Sigma P
+    double* ZR = PQ + sq;      // Z^T R (current)
+    double* ZRn = ZR + sq;     // Z^T R (next)
+    double* CA = ZRn + sq;     // alpha
+    double* CB = CA + sq;      // beta
+    double* part = CB + sq;    // Gram partials
+    int* gact_d = (int*)((char*)part + gram_partial_bytes(n, nrhs, bs));
+    int* flag_d = gact_d + ng;
+    std::vector<int> gact(ng), flag(ng), broken(ng, 0);
+    auto group_state = [&]() {
+      int na = 0;
+      for (int g = 0; g < ng; ++g) {
+        bool any = false;
+        for (int c = g * bs; c < std::min(nrhs, (g + 1) * bs); ++c) any |= !col_converged(c);
+        gact[g] = any && !broken[g];
+        na += gact[g];
+      }
+      return na;
+    };
+    auto push_groups = [&]() -> int {
+      HIP_TRY(ctx, hipMemcpyAsync(gact_d, gact.data(), ng * sizeof(int), hipMemcpyHostToDevice, s));
+      return MPCR_OK;
+    };
+    auto take_flags = [&]() -> int {  // groups whose s x s system broke down leave the block iteration
+      HIP_TRY(ctx, hipMemcpyAsync(flag.data(), flag_d, ng * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      for (int g = 0; g < ng; ++g)
+        if (flag[g]) broken[g] = 1;
+      return MPCR_OK;
+    };
+    int nga = group_state();
+    if ((rc = push_groups()) != MPCR_OK) return rc;
+    if (nga > 0) {
+      if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;  // Z = M^-1 R
+      HIP_TRY(ctx, launch_copy_cols((int)b.N, nrhs, b.Z, ld, b.P, ld, s));
+      HIP_TRY(ctx, launch_group_gram(n, nrhs, bs, b.Z, b.R, ld, part, ZR, 1.0, s));
+    }
+    while (nga > 0 && it < o.max_iter) {
+      // Q = -Sigma P; PQ = P^T Sigma P; alpha = PQ^-1 ZR
+      HIP_TRY(ctx, op.residual(nullptr, b.P, b.Q, ld, nrhs, s));
+      HIP_TRY(ctx, launch_group_gram(n, nrhs, bs, b.P, b.Q, ld, part, PQ, -1.0, s));
+      HIP_TRY(ctx, launch_group_spd_solve(nrhs, bs, PQ, ZR, gact_d, CA, flag_d, s));
+      if ((rc = take_flags()) != MPCR_OK) return rc;
+      ++it;
+      HIP_TRY(ctx, launch_group_axpy(n, nrhs, bs, b.P, CA, 1.0, b.X, ld, s));    // X += P alpha
+      if (o.recompute > 0 && it % o.recompute == 0) {
+        HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+        r_true = true;
+      } else {
+        HIP_TRY(ctx, launch_group_axpy(n, nrhs, bs, b.Q, CA, 1.0, b.R, ld, s));  // R -= Sigma P alpha
+        r_true = false;
+      }
+      if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+      bool check = false;  // a group whose columns all meet the tolerance is confirmed with the true residual
+      for (int g = 0; g < ng; ++g) {
+        if (!gact[g]) continue;
+        bool all = true;
+        for (int c = g * bs; c < std::min(nrhs, (g + 1) * bs); ++c) all &= col_converged(c);
+        check |= all;
+      }
+      if (check) {
+        HIP_TRY(ctx, op.residual(b.B, b.X, b.W, ld, nrhs, s));
+        if ((rc = fetch_stats(b.W)) != MPCR_OK) return rc;
+        HIP_TRY(ctx, launch_copy_cols(n, nrhs, b.W, ld, b.R, ld, s));
+        r_true = true;
+      }
+      nga = group_state();
+      if ((rc = push_groups()) != MPCR_OK) return rc;
+      if (nga == 0 || it >= o.max_iter) break;
+      // Z = M^-1 R; beta = ZR^-1 ZRn; P = Z + P beta
+      if ((rc = tile_solve(ctx, f, b, b.R, b.Z, b.W)) != MPCR_OK) return rc;
+      HIP_TRY(ctx, launch_group_gram(n, nrhs, bs, b.Z, b.R, ld, part, ZRn, 1.0, s));
+      HIP_TRY(ctx, launch_group_spd_solve(nrhs, bs, ZR, ZRn, gact_d, CB, flag_d, s));
+      if ((rc = take_flags()) != MPCR_OK) return rc;
+      HIP_TRY(ctx, hipMemcpyAsync(ZR, ZRn, sq * 8, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, launch_group_xpyc(n, nrhs, bs, b.Z, CB, b.P, ld, s));
+      nga = group_state();
+      if ((rc = push_groups()) != MPCR_OK) return rc;
+    }
+    // groups that broke down finish with PCG from their current iterate
+    bool any_broken = false;
+    for (int g = 0; g < ng; ++g) any_broken |= broken[g] != 0;
+    if (any_broken && it < o.max_iter) {
+      if (!r_true) {
+        HIP_TRY(ctx, op.residual(b.B, b.X, b.R, ld, nrhs, s));
+        if ((rc = fetch_stats(b.R)) != MPCR_OK) return rc;
+        r_true = true;
+      }
+      nact = 0;
+      for (int c = 0; c < nrhs; ++c) {
+        act[c] = broken[c / bs] && !col_converged(c);
+        nact += act[c];
+      }
+      if ((rc = push_active()) != MPCR_OK) return rc;
+      if (nact > 0 && (rc = pcg_loop()) != MPCR_OK) return rc;
     }
   }
   // final true residual and statistics (already current when the last step
@@ -775,6 +1002,9 @@ void ctx_release_workspace(mpcr_ctx* ctx) {
   dfree(ctx->arena, ctx->ws_vec);
   ctx->ws_vec = nullptr;
   ctx->ws_vec_bytes = 0;
+  dfree(ctx->arena, ctx->ws_kry);
+  ctx->ws_kry = nullptr;
+  ctx->ws_kry_bytes = 0;
   dfree(ctx->arena, ctx->ws_gemm);
   ctx->ws_gemm = nullptr;
   ctx->ws_gemm_bytes = 0;
@@ -914,6 +1144,7 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     free_factor(ctx->ws_factor);
     dfree(ctx->arena, ctx->ws_locs);
     dfree(ctx->arena, ctx->ws_vec);
+    dfree(ctx->arena, ctx->ws_kry);
     dfree(ctx->arena, ctx->ws_gemm);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     drain_timing(ctx);
@@ -1205,7 +1436,7 @@ int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double*
   const bool do_ref = d_A_fp64 && opts && opts->max_iter > 0;
   if (do_ref) {
     CHECK_ARG(ctx, lda >= fc->n, "lda < n");
-    CHECK_ARG(ctx, opts->tol > 0 && opts->solver >= 0 && opts->solver <= 1 && opts->recompute >= 0, "bad opts");
+    CHECK_ARG(ctx, refine_opts_ok(*opts), "bad opts");
   }
   auto* f = const_cast<mpcr_factor*>(fc);
   DeviceGuard g(ctx->device);
@@ -1254,8 +1485,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
       for (int64_t j = 0; j <= i; ++j) m[i * nt + j] = F64;
   }
   const int64_t nt = (n + nb - 1) / nb;
-  if (opts) CHECK_ARG(ctx, opts->tol > 0 && opts->solver >= 0 && opts->solver <= 1 && opts->recompute >= 0 &&
-                               opts->max_iter >= 0 && (opts->residual == 0 || opts->residual == 1) &&
+  if (opts) CHECK_ARG(ctx, refine_opts_ok(*opts) && (opts->residual == 0 || opts->residual == 1) &&
                                (opts->promote_on_breakdown == 0 || opts->promote_on_breakdown == 1) &&
                                (opts->direct_eta == 0 || opts->direct_eta == 1),
                       "bad refinement options");
@@ -1391,7 +1621,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     }
     if (diag) diag->converged = 1;
   } else {
-    mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0, 0, 0};
+    mpcr_refine_opts_t o = opts ? *opts : mpcr_refine_opts_t{1e-9, 0, 0, 20, 0, 0, 0, 0, 0.0, 0};
     SigmaOp op;
     op.ctx = ctx;
     if (stored_residual) {

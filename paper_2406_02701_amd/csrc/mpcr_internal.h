@@ -291,6 +291,33 @@ hipError_t launch_loglik(int n, int nrhs, const double* logdet, const double* qu
 hipError_t launch_quad_refined(int n, int nrhs, const double* Z, const double* X, const double* R, int64_t ld,
                                double* partial, double* quad, hipStream_t s);
 
+// Krylov refinement variants (krylov.hip).  Block PCG works on groups of at
+// most KRYLOV_MAX_BLOCK consecutive right-hand sides.
+constexpr int KRYLOV_MAX_BLOCK = 32;
+size_t gram_partial_bytes(int n, int nrhs, int bs);
+// G[g] = sign * A_g^T B_g for every group g of bs consecutive columns (bs x bs, column-major)
+hipError_t launch_group_gram(int n, int nrhs, int bs, const double* A, const double* B, int64_t ld,
+                             double* partial, double* G, double sign, hipStream_t s);
+hipError_t launch_group_spd_solve(int nrhs, int bs, const double* G, const double* F, const int* active, double* C,
+                                  int* flag, hipStream_t s);
+hipError_t launch_group_axpy(int n, int nrhs, int bs, const double* X, const double* C, double sign, double* Y,
+                             int64_t ld, hipStream_t s);
+hipError_t launch_group_xpyc(int n, int nrhs, int bs, const double* X, const double* C, double* Y, int64_t ld,
+                             hipStream_t s);
+hipError_t launch_col_dot_strided(int n, int nrhs, const double* A, const double* B, int64_t ld, double* partial,
+                                  double* out, int64_t stride, hipStream_t s);
+hipError_t launch_axpy_strided(int n, int nrhs, const double* a, int64_t stride, double sign, const double* X,
+                               double* Y, int64_t ld, hipStream_t s);
+hipError_t launch_scale_cols(int n, int nrhs, const double* f, const double* X, double* Y, int64_t ld,
+                             hipStream_t s);
+hipError_t launch_gmres_start(int nrhs, int m, const double* dot, const int* active, double* beta, double* g,
+                              double* inv, hipStream_t s);
+hipError_t launch_gmres_rotate(int nrhs, int m, int j, const double* dot, const int* run, double* H, double* cs,
+                               double* sn, double* g, double* out, hipStream_t s);
+hipError_t launch_gmres_inv(int nrhs, const double* norm, const int* cont, double* inv, hipStream_t s);
+hipError_t launch_gmres_backsolve(int nrhs, int m, const double* H, const double* g, const int* steps, double* y,
+                                  hipStream_t s);
+
 // I + diag(w) Sigma diag(w) into the tile store (Sigma from the sites)
 hipError_t launch_tiles_from_weighted_covariance(const TileView& tv, const double* locs, const mpcr_theta_t& th,
                                                  const double* w, hipStream_t s);

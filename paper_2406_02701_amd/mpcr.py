@@ -39,7 +39,8 @@ class mpcr_theta_t(C.Structure):
 
 class mpcr_refine_opts_t(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("solver", C.c_int), ("recompute", C.c_int),
-                ("residual", C.c_int), ("promote_on_breakdown", C.c_int), ("direct_eta", C.c_int)]
+                ("residual", C.c_int), ("promote_on_breakdown", C.c_int), ("direct_eta", C.c_int),
+                ("gmres_m", C.c_int), ("gmres_inner_tol", C.c_double), ("block_size", C.c_int)]
 
 
 class mpcr_diag_t(C.Structure):

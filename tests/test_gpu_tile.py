@@ -299,7 +299,7 @@ def test_mixed_refined_solve_reaches_fp64(g):
     dS, dB, dX = gu.dev(S), gu.dev(B), gu.empty(n, 4)
     Xref = dense.cholesky_solve(np.linalg.cholesky(S), B)
     sig_inf = np.max(np.sum(np.abs(S), axis=1))
-    for solver in (0, 1):
+    for solver in (0, 1, 2, 3):
         opts = mpcr.mpcr_refine_opts_t(1e-13, 100, solver, 20, 0)
         diag = mpcr.mpcr_diag_t()
         ctx.check(mpcr.mpcr_potrs(ctx.ptr, f, 4, dB.data_ptr(), n, dX.data_ptr(), n, dS.data_ptr(), n,
