@@ -3,9 +3,9 @@
 Workload (the mixed-precision tile Cholesky configuration): n = 32768 sites
 drawn uniformly in the unit square, Matern nu = 3/2 covariance (variance 1,
 range 0.05, nugget 1e-6), tiles nb = 512, 16 N(0,1) observation vectors,
-FP64 iterative refinement (PCG) to a normwise backward error below the 1e-9
-bar (default 1e-13, so that the quadratic forms match the FP64 path), and
-the log-likelihood.
+FP64 refinement (PCG, GMRES-IR or block PCG) to a normwise backward error
+below the 1e-9 bar (default 1e-13, so that the quadratic forms match the FP64
+path), and the log-likelihood.
 
 One step = one mpcr_gauss_loglik call: Morton ordering, covariance
 generation into the tile formats, the tile factorisation, log-determinant,
@@ -19,11 +19,11 @@ Precision map: the band map (FP64 for tile distance d <= 2, FP32 for
 far tiles make the matrix indefinite); the library reports NOT_SPD for it
 and the bench records that outcome.  The map study promotes the same band
 map tile by tile by norm guards u_p * max|Sigma_tile| <= g * nugget for
-several g and reports, per guard, the time, the log-determinant and
-log-likelihood errors against the FP64 path, and the same with refinement
-stopped at the bar alone.  The headline is the fastest guard whose
-log-likelihoods match the FP64 path to 1e-6; the fastest guard that only
-holds the bar is reported beside it.
+several g and reports, per guard and refinement solver, the time, the
+log-determinant and log-likelihood errors against the FP64 path, and the
+same with refinement (PCG) stopped at the bar alone.  The headline is the
+fastest (guard, solver) pair whose log-likelihoods match the FP64 path to
+1e-6; the fastest guard that only holds the bar is reported beside it.
 
 Further lines: the 1024-site FP64 workload and the 65536-site workload
 (256 RHS), the multi-format GEMM sweep, the serving loop (capacity and a
@@ -77,6 +77,10 @@ def parse():
                          "of the nugget: a tile keeps its band format p only if u_p max|Sigma_tile| <= guard * nugget")
     ap.add_argument("--study-guards", type=float, nargs="*", default=[0.003, 0.01, 0.02, 0.03, 0.1, 0.3, 1.0],
                     help="guards (multiples of the nugget) of the map study")
+    ap.add_argument("--study-solvers", nargs="*", default=["pcg", "gmres", "bpcg"],
+                    choices=["pcg", "ir", "gmres", "bpcg"],
+                    help="refinement solvers timed for every map of the study (PCG, classical IR, GMRES-IR, "
+                         "block PCG)")
     ap.add_argument("--loglik-match", type=float, default=1e-6,
                     help="headline map: the fastest of the study whose log-likelihoods match the FP64 path to this "
                          "relative error")
@@ -116,6 +120,10 @@ class Lib:
         ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self.m.check(self.m.mpcr_ctx_kernel_stats(ctx, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
         return ms.value, n.value, fl.value
+
+
+SOLVER_CODE = {"pcg": 0, "ir": 1, "gmres": 2, "bpcg": 3}
+SOLVER_NAME = {"pcg": "pcg", "ir": "iterative refinement", "gmres": "GMRES-IR", "bpcg": "block pcg"}
 
 
 def measured_traffic(kind, guard):
@@ -469,6 +477,11 @@ def main():
     # are far from the FP64 ones on this covariance (cond ~ 1e8)
     study = []
     opts_bar = mp.mpcr_refine_opts_t(1e-9, 100, 0, 20, args.residual)
+
+    def solver_opts(name):
+        o = mp.mpcr_refine_opts_t(args.tol, 100, SOLVER_CODE[name], 20, args.residual)
+        return o
+
     for gmul in args.study_guards:
         gm_ = guarded_map(gmul)
         st, ll, d = lib.loglik(ctx_m, n, dl, dz, nrhs, th, gm_, nb, opts)
@@ -477,24 +490,41 @@ def main():
         if st == mp.MPCR_OK and d.converged:
             fl_by = list(d.flops_by_prec)
             ideal = sum(fl_by[p] / (PEAK_TFLOPS[p] * 1e12) for p in range(5))
-            t, ll, d = timed_steps(lib, ctx_m, argparse.Namespace(warmup=0, steps=2),
-                                   lambda: lib.loglik(ctx_m, n, dl, dz, nrhs, th, gm_, nb, opts))
-            rec.update(ms_per_step=t * 1e3, speedup_vs_fp64=t_64 / t, iters=d.iters, eta=d.eta,
-                       ideal_ms_at_mfma_peak=ideal * 1e3, ideal_speedup=ideal64 / ideal,
-                       logdet_err_vs_fp64=d.logdet - d_64.logdet,
-                       loglik_rel_err_vs_fp64=float(np.max(np.abs(ll - ll_64) / np.abs(ll_64))))
+            rec.update(ideal_ms_at_mfma_peak=ideal * 1e3, ideal_speedup=ideal64 / ideal,
+                       logdet_err_vs_fp64=d.logdet - d_64.logdet, by_solver={})
+            for sname in args.study_solvers:
+                so = solver_opts(sname)
+                st, ll, d = lib.loglik(ctx_m, n, dl, dz, nrhs, th, gm_, nb, so)      # untimed first call
+                if st != mp.MPCR_OK or not d.converged:
+                    rec["by_solver"][sname] = {"status": mp.STATUS_NAMES.get(st, st), "converged": bool(d.converged)}
+                    continue
+                t, ll, d = timed_steps(lib, ctx_m, argparse.Namespace(warmup=0, steps=2),
+                                       lambda: lib.loglik(ctx_m, n, dl, dz, nrhs, th, gm_, nb, so))
+                rec["by_solver"][sname] = {
+                    "ms_per_step": t * 1e3, "speedup_vs_fp64": t_64 / t, "iters": d.iters, "eta": d.eta,
+                    "t_solve_ms": d.t_solve_ms,
+                    "loglik_rel_err_vs_fp64": float(np.max(np.abs(ll - ll_64) / np.abs(ll_64)))}
+            done = {k: v for k, v in rec["by_solver"].items() if "ms_per_step" in v}
+            if done:
+                best = min(done, key=lambda k: done[k]["ms_per_step"])
+                rec.update(solver=best, **{k: done[best][k] for k in ("ms_per_step", "speedup_vs_fp64", "iters",
+                                                                      "eta", "loglik_rel_err_vs_fp64")})
             t9, ll9, d9 = timed_steps(lib, ctx_m, argparse.Namespace(warmup=0, steps=2),
                                       lambda: lib.loglik(ctx_m, n, dl, dz, nrhs, th, gm_, nb, opts_bar))
             rec["bar_only"] = {"tol": 1e-9, "ms_per_step": t9 * 1e3, "speedup_vs_fp64": t_64 / t9,
                                "iters": d9.iters, "eta": d9.eta, "rel_resid2": d9.rel_resid2,
                                "loglik_rel_err_vs_fp64": float(np.max(np.abs(ll9 - ll_64) / np.abs(ll_64)))}
         study.append(rec)
-    # headline: the fastest map of the study whose log-likelihoods match the
-    # FP64 path to 1e-6 (the log-determinant is the part refinement cannot fix)
-    ok = [r for r in study if r.get("loglik_rel_err_vs_fp64", 1.0) <= args.loglik_match]
-    head = min(ok, key=lambda r: r["ms_per_step"]) if ok else None
-    head_gmul = head["guard_x_nugget"] if head else args.guard
+    # headline: the fastest (map, solver) pair of the study whose log-
+    # likelihoods match the FP64 path to 1e-6 (the log-determinant is the part
+    # refinement cannot fix)
+    cands = [(r["guard_x_nugget"], sname, v["ms_per_step"]) for r in study for sname, v in r.get("by_solver", {}).items()
+             if v.get("loglik_rel_err_vs_fp64", 1.0) <= args.loglik_match]
+    head = min(cands, key=lambda c: c[2]) if cands else None
+    head_gmul = head[0] if head else args.guard
+    head_solver = head[1] if head else "pcg"
     head_map = guarded_map(head_gmul)
+    opts = solver_opts(head_solver)
     guarded = guarded_map(args.guard)
 
     # headline, timed with kernel profiling
@@ -551,7 +581,7 @@ def main():
                    "map": f"band d<=2 fp64 / 3-8 fp32 / >=9 bf16, norm-guarded (u_p max|tile| <= {head_gmul:g} "
                           f"nugget): the fastest guard of the map study whose log-likelihoods match the FP64 path "
                           f"to {args.loglik_match:g}",
-                   "refine": f"pcg, normwise backward error <= {args.tol:g} (bar: 1e-9), "
+                   "refine": f"{SOLVER_NAME[head_solver]}, normwise backward error <= {args.tol:g} (bar: 1e-9), "
                              f"{'stored FP64 tiles' if args.residual else 'matrix-free'} residual"},
         "fp64_path": {"value": flops / t_64 / 1e12, "ms_per_step": t_64 * 1e3,
                       "eta_untimed_check": d_64eta.eta, "rel_resid2_untimed_check": d_64eta.rel_resid2,
@@ -559,7 +589,7 @@ def main():
                       "t_factor_ms": d_64.t_factor_ms, "t_solve_ms": d_64.t_solve_ms,
                       "ideal_ms_at_mfma_peak": ideal64 * 1e3},
         "speedup_vs_fp64": t_64 / t_mix,
-        "mixed": {"guard_x_nugget": head_gmul, "eta": d_mix.eta, "rel_resid2": d_mix.rel_resid2,
+        "mixed": {"guard_x_nugget": head_gmul, "solver": head_solver, "eta": d_mix.eta, "rel_resid2": d_mix.rel_resid2,
                   "iters": d_mix.iters, "converged": bool(d_mix.converged), "logdet": d_mix.logdet,
                   "logdet_err_vs_fp64": d_mix.logdet - d_64.logdet,
                   "logdet_rel_err_vs_fp64": abs(d_mix.logdet - d_64.logdet) / abs(d_64.logdet),
