@@ -127,16 +127,39 @@ __device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, 
   }
 }
 
+// Raw storage element of a tile format and its widening to FP64: the wide
+// update loop holds its prefetched tile values in the storage width and widens
+// them at the MFMA, which keeps the narrow formats' register footprint small.
+template <int F> struct RawOf { using T = double; };
+template <> struct RawOf<F32> { using T = float; };
+template <> struct RawOf<F16> { using T = uint16_t; };
+template <> struct RawOf<BF16> { using T = uint16_t; };
+template <> struct RawOf<F8> { using T = uint8_t; };
+template <int F>
+__device__ __forceinline__ typename RawOf<F>::T ldraw(const void* p, int64_t i) {
+  return ((const typename RawOf<F>::T*)p)[i];
+}
+template <int F>
+__device__ __forceinline__ double widen(typename RawOf<F>::T v, double mul) {
+  if constexpr (F == F64) return v;
+  else if constexpr (F == F32) return (double)v;
+  else if constexpr (F == F16) return (double)f16_to_f32(v);
+  else if constexpr (F == BF16) return (double)bf16_to_f32(v);
+  else return (double)e4m3_to_f32(v) * mul;  // FP8 tiles hold codes of v 2^s
+}
+
 // Wide variant for the update launches with many tiles: one workgroup owns 64
 // output rows (four 16-row blocks that share each right-hand-side value it
 // loads), its SW4 waves split the contraction into equal parts.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t row0, int k0, int k1, const double* V,
                                            int64_t vsk, int lane, d4 (&acc)[4], double mul) {
-  constexpr int U = 4;  // k4 steps per batch
+  constexpr int U = 2;  // k4 steps per batch
+  using RT = typename RawOf<F>::T;
   const int q = lane >> 4;
-  double a[4][U], b[U], an[4][U], bn[U];
-  auto load = [&](int kk, double (*da)[U], double* db) {
+  RT a[4][U], an[4][U];
+  double b[U], bn[U];
+  auto load = [&](int kk, RT (*da)[U], double* db) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t k = kk + 4 * u + q;
@@ -144,8 +167,7 @@ __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t r
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         const int64_t row = row0 + 16 * h;
-        da[h][u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
-        if constexpr (F == F8) da[h][u] *= mul;
+        da[h][u] = !in ? RT(0) : TRANS ? ldraw<F>(M, row * ldm + k) : ldraw<F>(M, k * ldm + row);
       }
       db[u] = (V && in) ? V[k * vsk] : 0.0;
     }
@@ -157,7 +179,8 @@ __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t r
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int h = 0; h < 4; ++h) acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][u], b[u], acc[h], 0, 0, 0);
+      for (int h = 0; h < 4; ++h)
+        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(widen<F>(a[h][u], mul), b[u], acc[h], 0, 0, 0);
     if (more) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -215,7 +238,9 @@ __device__ void tile_mfma4_any(const void* M, int f, double mul, int nb, int r0,
 }
 
 // Each step solves one block (diag kernel) and then updates the rest (update
-// kernel).  The diag kernel also writes the solved block by rows into stage
+// kernel).  The update kernels hold every tile format's loop; they are held to
+// 128 VGPRs so that two 512-thread workgroups fit on a CU (with 156 VGPRs only
+// one did, which halved their bandwidth).  The diag kernel also writes the solved block by rows into stage
 // (nb x nrhs, row stride nrhs), which the update kernel reads as its
 // right-hand side: lanes then read whole rows of 16 values.
 
@@ -229,7 +254,7 @@ __global__ __launch_bounds__(STHREADS) void k_fwd_diag(int nb, const double* Lin
                        stage);
 }
 
-__global__ __launch_bounds__(STHREADS) void k_fwd_update(TileView tv, int k, double* R, const double* stage,
+__global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_fwd_update(TileView tv, int k, double* R, const double* stage,
                                                          int64_t ld, int nrhs) {
   if (*tv.info) return;
   __shared__ double red[SW][16][17];
@@ -249,7 +274,7 @@ __global__ __launch_bounds__(STHREADS) void k_bwd_diag(int nb, const double* Lin
                         1.0, stage);
 }
 
-__global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, double* V, const double* stage,
+__global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_bwd_update(TileView tv, int k, double* V, const double* stage,
                                                          int64_t ld, int nrhs) {
   if (*tv.info) return;
   __shared__ double red[SW][16][17];
@@ -259,7 +284,7 @@ __global__ __launch_bounds__(STHREADS) void k_bwd_update(TileView tv, int k, dou
                       V + (int64_t)i * nb, ld, nrhs, 1, red);
 }
 
-__global__ __launch_bounds__(64 * SW4) void k_fwd_update4(TileView tv, int k, double* R, const double* stage, int64_t ld,
+__global__ __launch_bounds__(64 * SW4) __attribute__((amdgpu_waves_per_eu(4))) void k_fwd_update4(TileView tv, int k, double* R, const double* stage, int64_t ld,
                                                      int nrhs) {
   if (*tv.info) return;
   __shared__ double red[SW4][64][17];
@@ -269,7 +294,7 @@ __global__ __launch_bounds__(64 * SW4) void k_fwd_update4(TileView tv, int k, do
                         R + (int64_t)i * nb, ld, nrhs, red);
 }
 
-__global__ __launch_bounds__(64 * SW4) void k_bwd_update4(TileView tv, int k, double* V, const double* stage, int64_t ld,
+__global__ __launch_bounds__(64 * SW4) __attribute__((amdgpu_waves_per_eu(4))) void k_bwd_update4(TileView tv, int k, double* V, const double* stage, int64_t ld,
                                                      int nrhs) {
   if (*tv.info) return;
   __shared__ double red[SW4][64][17];
