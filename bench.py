@@ -70,7 +70,12 @@ def parse():
     ap.add_argument("--guard-n65536", type=float, default=1e-4,
                     help="norm guard of the 65536-site map, as a multiple of the nugget")
     ap.add_argument("--serve-count", type=int, default=4096, help="serving requests (0 = skip the serving leg)")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg and print its results")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-queues", type=int, default=16,
+                    help="HIP hardware queues of the serving process (GPU_MAX_HW_QUEUES; the serving leg runs in a "
+                         "child process with this setting so that every slot's streams get queues of their own; "
+                         "0 = run it in this process)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--guard", type=float, default=0.01,
                     help="fallback guard of the headline map (used if no map of the study matches), as a multiple "
@@ -124,6 +129,25 @@ class Lib:
 
 SOLVER_CODE = {"pcg": 0, "ir": 1, "gmres": 2, "bpcg": 3}
 SOLVER_NAME = {"pcg": "pcg", "ir": "iterative refinement", "gmres": "GMRES-IR", "bpcg": "block pcg"}
+
+
+def serving_leg(lib, args):
+    """The serving results, from a child process started with
+    GPU_MAX_HW_QUEUES = args.serve_queues (HIP reads it at start-up; with its
+    default of 4 queues the slots' streams share in-order queues and wait on
+    each other), or from this process when args.serve_queues is 0."""
+    if args.serve_queues <= 0:
+        return serving_bench(lib, args.serve_count, args.serve_slots, args.serve_budget_gb)
+    import subprocess
+    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(args.serve_queues))
+    cmd = [sys.executable, os.path.abspath(__file__), "--serve-only", "--serve-count", str(args.serve_count),
+           "--serve-slots", str(args.serve_slots), "--serve-budget-gb", str(args.serve_budget_gb)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True)
+    if r.returncode != 0:
+        return {"error": f"serving child exited with {r.returncode}", "stderr_tail": r.stderr[-2000:]}
+    out = json.loads(r.stdout.strip().splitlines()[-1])["serving"]
+    out["hw_queues"] = args.serve_queues
+    return out
 
 
 def measured_traffic(kind, guard):
@@ -256,9 +280,11 @@ def gemm_sweep(lib, torch, steps):
 def serving_bench(lib, count, slots, budget_gb, seed=6):
     """Log-likelihood requests with n log-uniform in [256, 8192] and their own
     parameters (variance U(0.5,2), range U(0.02,0.3), nu in {1/2, 3/2, 5/2},
-    nugget 1e-6), one observation vector each.  Phase 1 submits all requests at
-    once (closed-loop capacity, solves/s); phase 2 replays Poisson arrivals at
-    0.8 x that capacity and reports the latency (done - arrival) percentiles."""
+    nugget 1e-6), one observation vector each.  The closed-loop capacity
+    (solves/s) is the median of three runs that submit all requests at once;
+    Poisson arrivals are then replayed at 0.5, 0.8 and 1.0 x that capacity,
+    each reporting the latency (done - arrival) percentiles and whether the
+    served rate kept up with the offered one."""
     mp = lib.m
     w = synth.WORKLOADS["serve_4096"]
     reqs = synth.serving_requests(count, seed, w["n_lo"], w["n_hi"])
@@ -408,6 +434,10 @@ def main():
     mp = lib.m
     if args.gemm_only:
         print(json.dumps({"gemm_sweep_8192": gemm_sweep(lib, torch, args.steps)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_bench(lib, args.serve_count, args.serve_slots, args.serve_budget_gb)}),
+              flush=True)
         return
     w = dict(synth.WORKLOADS["mixed_n32768"])
     if args.n:
@@ -621,7 +651,7 @@ def main():
     if not args.no_gemm:
         line["gemm_sweep_8192"] = gemm_sweep(lib, torch, 3)
     if args.serve_count > 0:
-        line["serving"] = serving_bench(lib, args.serve_count, args.serve_slots, args.serve_budget_gb)
+        line["serving"] = serving_leg(lib, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_n, n))
     print(json.dumps(line), flush=True)

@@ -428,9 +428,13 @@ int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m
  * factor breaks down is refactored with promoted tiles when
  * refine.promote_on_breakdown is 1, and recomputed with all tiles FP64 when
  * it still fails and fallback_fp64 is 1.  refine.residual must be 0 (the
- * footprint estimate assumes the matrix-free residual).  A
- * request's arithmetic does not depend on what else is running: results are
- * the same alone and in a mix. */
+ * footprint estimate assumes the matrix-free residual) and refine.solver 0 or
+ * 1 (PCG or IR: the Krylov workspaces of GMRES-IR and block PCG are not in the
+ * estimate).  A request's arithmetic does not depend on what else is running:
+ * results are the same alone and in a mix.  HIP maps streams onto
+ * GPU_MAX_HW_QUEUES in-order hardware queues per process (4 by default), so
+ * slots whose streams share a queue wait on each other; with more than two
+ * slots, start the process with GPU_MAX_HW_QUEUES >= max_slots. */
 typedef struct mpcr_server mpcr_server;
 
 typedef struct {
