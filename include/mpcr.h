@@ -191,6 +191,14 @@ const char* mpcr_version(void);
  * SYRK or TRSM tile, nb^3/3 per POTRF or inversion, 2 N^2 nrhs per sweep,
  * 2 n^2 nrhs per residual).  Reset clears all kinds. */
 int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on);
+/* How GEMM updates of FP32 tiles form their products (the tile stays FP32 and
+ * each update result is rounded to FP32 once).  on = 1 (default): both
+ * operands, converted to FP32, are split exactly into three BF16 parts
+ * x = h + m + l and the six products h h, h m, m h, h l, l h, m m are
+ * accumulated in FP32 on the BF16 MFMA (the dropped products are below
+ * 2^-23 |a b|, so the accuracy is FP32's; gfx950's BF16 MFMA is 16 times
+ * faster than its FP32 MFMA).  on = 0: the FP32 MFMA.  Errors: MPCR_ERR_ARG. */
+int mpcr_ctx_set_fp32_split(mpcr_ctx* ctx, int on);
 int mpcr_ctx_reset_stats(mpcr_ctx* ctx);
 int mpcr_ctx_kernel_stats(const mpcr_ctx* ctx, int kind, double* h_total_ms, int64_t* h_launches,
                           double* h_flops);

@@ -105,6 +105,7 @@ struct mpcr_ctx {
   std::vector<Pending> pending;
   double k_ms[NKIND] = {0}, k_flops[NKIND] = {0};
   int64_t k_launches[NKIND] = {0};
+  int fp32_split = 1;              // FP32 tile updates through the BF16 MFMA (three-way split)
   // lookahead: a second stream for the bulk of each trailing update
   hipStream_t upd = nullptr;        // trailing updates of the factorisation
   hipStream_t col = nullptr;        // updates of the next panel column
@@ -465,7 +466,7 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
       } else if (which == 0 && f->map[(k + 1) * nt + k] == F64) {
         HIP_TRY(ctx, timed(ctx, s, 10, fl, [&] { return launch_syrk_tile(tv, (int)k, (int)k + 1, s); }));
       } else {
-        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s); }));
+        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s, ctx->fp32_split); }));
       }
     }
     return MPCR_OK;
@@ -1163,6 +1164,12 @@ const char* mpcr_last_error(const mpcr_ctx* ctx) { return ctx ? ctx->err.c_str()
 int mpcr_ctx_set_profiling(mpcr_ctx* ctx, int on) {
   if (!ctx) return MPCR_ERR_ARG;
   ctx->profiling = on != 0;
+  return MPCR_OK;
+}
+
+int mpcr_ctx_set_fp32_split(mpcr_ctx* ctx, int on) {
+  if (!ctx || (on != 0 && on != 1)) return set_err(ctx, MPCR_ERR_ARG, "mpcr_ctx_set_fp32_split: bad arguments");
+  ctx->fp32_split = on;
   return MPCR_OK;
 }
 

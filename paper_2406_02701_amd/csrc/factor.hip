@@ -418,6 +418,189 @@ __global__ __launch_bounds__(256) void k_update_mmajor(TileView tv, int k, const
 }
 
 // ---------------------------------------------------------------------------
+// FP32 output tiles through the BF16 MFMA.  gfx950's dense BF16 rate is 16
+// times its FP32 rate, so an FP32 product can be formed from BF16 pieces:
+// each operand, converted to FP32 as in the FP32 update, is split exactly
+// into three BF16 numbers x = h + m + l (h = bf16(x), m = bf16(x - h),
+// l = x - h - m; every difference is exact by Sterbenz's lemma and l needs at
+// most 8 significant bits), and a b is accumulated as
+//   ah bh + ah bm + am bh + ah bl + al bh + am bm
+// in FP32 on v_mfma_f32_16x16x32_bf16 (which returns the exact FP32-rounded
+// sums).  The three dropped products am bl + al bm + al bl are below
+// 2^-23 |a b|, so every update keeps FP32-level accuracy; the output tile is
+// rounded to FP32 as in the FP32 update.  One 128 x 128 block of C per
+// workgroup, 8 waves of 64 x 32, k chunks of 32; the three planes of both
+// operands (61 KB) sit in one LDS buffer so that two workgroups share a CU.
+// ---------------------------------------------------------------------------
+constexpr int SBK = 32;          // k per chunk
+constexpr int SLDK = SBK + 8;    // LDS row (halfwords): 80-byte rows put the 16 rows of a fragment read on disjoint banks
+
+__device__ __forceinline__ void split3_bf16(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  // finite inputs: round to nearest even by adding half an ulp (ties to even)
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  h = (uint16_t)(u >> 16);
+  const float r1 = x - __uint_as_float((uint32_t)h << 16);
+  uint32_t v = __float_as_uint(r1);
+  v += 0x7fffu + ((v >> 16) & 1u);
+  m = (uint16_t)(v >> 16);
+  const float r2 = r1 - __uint_as_float((uint32_t)m << 16);
+  l = (uint16_t)(__float_as_uint(r2) >> 16);  // r2 has at most 8 significant bits: exact
+}
+
+// element idx of a tile (format SF) converted to FP32 (FP8 codes scaled back
+// by mul = 2^-s)
+template <int SF>
+__device__ __forceinline__ float load1_f32(const void* p, int64_t idx, double mul) {
+  if constexpr (SF == F64) return to_f32(((const double*)p)[idx]);
+  else if constexpr (SF == F32) return ((const float*)p)[idx];
+  else if constexpr (SF == F16) return f16_to_f32(((const uint16_t*)p)[idx]);
+  else if constexpr (SF == BF16) return bf16_to_f32(((const uint16_t*)p)[idx]);
+  else return to_f32((double)e4m3_to_f32(((const uint8_t*)p)[idx]) * mul);
+}
+
+using SplitBuf = uint16_t[3][UBM][SLDK];
+
+template <int FA, int FB>
+__device__ __forceinline__ void split_mainloop(const void* Ap, const void* Bp, double ma, double mb, int nb,
+                                               int64_t arow0, int64_t brow0, SplitBuf& As, SplitBuf& Bs,
+                                               f4 (&acc)[4][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  // staging: thread = one row (m) and 8 consecutive k of the chunk; a load
+  // instruction covers 64 consecutive rows of one k column (coalesced), and
+  // the split values go to LDS as one 16-byte vector per plane
+  const int mr = tid & (UBM - 1);
+  const int k0 = 8 * (tid / UBM);
+  float ra[8], rb[8];
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t col = kk + k0 + e;
+      ra[e] = load1_f32<FA>(Ap, col * nb + arow0 + mr, ma);
+      rb[e] = load1_f32<FB>(Bp, col * nb + brow0 + mr, mb);
+    }
+  };
+  auto sstore = [&]() {
+    u16x8 ah, am, al, bh, bm, bl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      uint16_t h, m, l;
+      split3_bf16(ra[e], h, m, l);
+      ah[e] = h;
+      am[e] = m;
+      al[e] = l;
+      split3_bf16(rb[e], h, m, l);
+      bh[e] = h;
+      bm[e] = m;
+      bl[e] = l;
+    }
+    *(u16x8*)&As[0][mr][k0] = ah;
+    *(u16x8*)&As[1][mr][k0] = am;
+    *(u16x8*)&As[2][mr][k0] = al;
+    *(u16x8*)&Bs[0][mr][k0] = bh;
+    *(u16x8*)&Bs[1][mr][k0] = bm;
+    *(u16x8*)&Bs[2][mr][k0] = bl;
+  };
+  gload(0);
+  sstore();
+  __syncthreads();
+  const int kq8 = 8 * (lane >> 4);
+  // one LDS buffer (two workgroups per CU): the next chunk is loaded into
+  // registers during this chunk's products and stored after a barrier
+  for (int kk = 0; kk < nb; kk += SBK) {
+    const bool more = kk + SBK < nb;
+    if (more) gload(kk + SBK);
+    u16x8 a[3][4], b[3][2];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[p][x] = *(const u16x8*)&As[p][wm * 64 + x * 16 + (lane & 15)][kq8];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) b[p][y] = *(const u16x8*)&Bs[p][wn * 32 + y * 16 + (lane & 15)][kq8];
+    }
+#define MPCR_MF(PA, PB)                                                                                   \
+  acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[PA][x]),              \
+                                                      __builtin_bit_cast(bf16x8, b[PB][y]), acc[x][y], 0, 0, 0)
+    // the small products first, the leading one last
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        MPCR_MF(1, 1);
+        MPCR_MF(0, 2);
+        MPCR_MF(2, 0);
+        MPCR_MF(0, 1);
+        MPCR_MF(1, 0);
+        MPCR_MF(0, 0);
+      }
+#undef MPCR_MF
+    if (more) {
+      __syncthreads();
+      sstore();
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(512) void k_update_f32_split(TileView tv, int k, const GemmTask* tasks) {
+  __shared__ __attribute__((aligned(16))) SplitBuf As;
+  __shared__ __attribute__((aligned(16))) SplitBuf Bs;
+
+  const int nb = tv.nb;
+  const int sub = nb / UBM;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int task = lb / (sub * sub);
+  const int blk = lb % (sub * sub);
+  const int bm = blk % sub, bn = blk / sub;
+  const GemmTask t = tasks[task];
+  if (t.i == t.j && bn > bm) return;
+  if (*tv.info) return;
+
+  const void* Ap = tv.tile(t.i, k);
+  const void* Bp = tv.tile(t.j, k);
+  const int fa = tv.tfmt(t.i, k), fb = tv.tfmt(t.j, k);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
+
+  f4 acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f4{0, 0, 0, 0};
+
+  const double ma = tv.tmul(t.i, k), mb = tv.tmul(t.j, k);
+#define MPCR_PAIR(FA, FB) \
+  case FA * 5 + FB: split_mainloop<FA, FB>(Ap, Bp, ma, mb, nb, arow0, brow0, As, Bs, acc); break;
+#define MPCR_ROW(FA) MPCR_PAIR(FA, F64) MPCR_PAIR(FA, F32) MPCR_PAIR(FA, F16) MPCR_PAIR(FA, BF16) MPCR_PAIR(FA, F8)
+  switch (fa * 5 + fb) {
+    MPCR_ROW(F64)
+    MPCR_ROW(F32)
+    MPCR_ROW(F16)
+    MPCR_ROW(BF16)
+    MPCR_ROW(F8)
+    default: break;
+  }
+#undef MPCR_ROW
+#undef MPCR_PAIR
+
+  void* Cp = tv.tile(t.i, t.j);  // FP32 (the update runs in the output tile's format)
+  const bool diag = (t.i == t.j);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = arow0 + wm * 64 + x * 16 + 4 * (lane >> 4) + r;
+        const int64_t C = brow0 + wn * 32 + y * 16 + (lane & 15);
+        if (diag && C > R) continue;
+        rmw_sub<F32>(Cp, C * nb + R, (double)acc[x][y][r]);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Updates of FP8 output tiles (the update runs in the output tile's format):
 // both operands are converted to FP8 on load with the scale of their own tile
 // (a stored FP8 tile keeps its codes; any other operand tile (i, k) is
@@ -637,13 +820,18 @@ hipError_t launch_panel_amax(const TileView& tv, int k, double* pamax, hipStream
 }
 
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
-                              hipStream_t s) {
+                              hipStream_t s, bool fp32_split) {
   if (ntasks == 0) return hipSuccess;
   const int sub = tv.nb / UBM;
   dim3 grid(ntasks * sub * sub);
   switch (cfmt) {
     case F64: k_update_kmajor<F64><<<grid, KMajor<F64>::NT, 0, s>>>(tv, k, tasks); break;
-    case F32: k_update_kmajor<F32><<<grid, KMajor<F32>::NT, 0, s>>>(tv, k, tasks); break;
+    case F32:
+      if (fp32_split)
+        k_update_f32_split<<<grid, 512, 0, s>>>(tv, k, tasks);
+      else
+        k_update_kmajor<F32><<<grid, KMajor<F32>::NT, 0, s>>>(tv, k, tasks);
+      break;
     case BF16: k_update_mmajor<BF16><<<grid, 256, 0, s>>>(tv, k, tasks); break;
     case F16: k_update_mmajor<F16><<<grid, 256, 0, s>>>(tv, k, tasks); break;
     default: return hipErrorInvalidValue;

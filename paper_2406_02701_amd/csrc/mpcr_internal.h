@@ -236,8 +236,10 @@ hipError_t launch_tile_update_fp8(const TileView& tv, int k, const GemmTask* tas
                                   float* ws32, unsigned* amax32, hipStream_t s);
 hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, const double* dinv, bool fp8_panel,
                              hipStream_t s);
+// fp32_split: FP32 output tiles through the BF16 MFMA with operands split
+// into three BF16 parts (FP32-level accuracy); else the FP32 MFMA
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
-                              hipStream_t s);
+                              hipStream_t s, bool fp32_split = false);
 hipError_t launch_logdet(const TileView& tv, double* out, hipStream_t s);
 hipError_t launch_trtri_diag(const TileView& tv, double* Linv, const double* dinv, hipStream_t s);
 

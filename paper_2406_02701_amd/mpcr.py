@@ -76,6 +76,7 @@ _SIGS = {
     "mpcr_ctx_destroy": (_i32, [_vp]),
     "mpcr_last_error": (C.c_char_p, [_vp]),
     "mpcr_ctx_set_profiling": (_i32, [_vp, _i32]),
+    "mpcr_ctx_set_fp32_split": (_i32, [_vp, _i32]),
     "mpcr_ctx_reset_stats": (_i32, [_vp]),
     "mpcr_ctx_kernel_stats": (_i32, [_vp, _i32, _P(_d), _P(_i64), _P(_d)]),
     "mpcr_tilemap_banded": (_i32, [_i64, _i64, _P(_i32), _P(_i32), _i32, _P(C.c_uint8)]),

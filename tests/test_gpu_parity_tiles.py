@@ -123,3 +123,49 @@ def test_mixed_factor_elementwise_vs_emulation(g, name):
             den += ref * ref
     print(f"case {name}: worst per-tile relative difference by format {worst}; gate {gate:.3g}", flush=True)
     assert math.sqrt(num / den) <= gate
+
+
+@pytest.mark.parametrize("split", [1, 0])
+def test_fp32_tiles_match_emulation_both_product_modes(g, split):
+    """FP64 near the diagonal, FP32 beyond, nb = 256 (two sub-blocks per tile):
+    with the FP32 products formed by the three-way BF16 split (split = 1) and
+    by the FP32 MFMA (split = 0), every FP32 tile agrees with the emulation
+    (exact products, one FP32 rounding per update) to the FP32 unit roundoff
+    in norm: the updates are a few percent of the entries of the dominant
+    matrix, so the accumulation errors of both modes stay below one FP32
+    rounding of the tile."""
+    from paper_2406_02701_amd import mpcr
+    gu, ctx = g
+    n, nb = 4096 - 37, 256
+    A = matrix(dict(n=n, rho=0.999, matrix="dominant"))
+    m = tiled.tilemap_banded(n, nb, ((1, "fp64"), (None, "fp32")))
+    nt = m.shape[0]
+    ctx.check(mpcr.mpcr_ctx_set_fp32_split(ctx.ptr, split))
+    try:
+        dA = gu.dev(A)
+        hm = gu.u8map(m)
+        tm = mpcr.tilemap(n, nb, hm)
+        f = ctypes.c_void_p()
+        info = ctypes.c_int64(-1)
+        ctx.check(mpcr.mpcr_potrf_tiled(ctx.ptr, n, dA.data_ptr(), n, ctypes.byref(tm), ctypes.byref(f),
+                                        ctypes.byref(info)))
+        dL = gu.empty(n, n)
+        ctx.check(mpcr.mpcr_factor_to_dense(ctx.ptr, f, dL.data_ptr(), n))
+        torch.cuda.synchronize()
+        L = gu.host(dL, (n, n))
+        mpcr.mpcr_factor_destroy(f)
+    finally:
+        ctx.check(mpcr.mpcr_ctx_set_fp32_split(ctx.ptr, 1))
+    E = tiled.tile_cholesky_emulated(A, nb, m)["L"][:n, :n]
+    u32 = ff.fmt_of(ff.CODE["fp32"]).unit_roundoff
+    worst = 0.0
+    for i in range(nt):
+        for j in range(i + 1):
+            sl = (slice(i * nb, min((i + 1) * nb, n)), slice(j * nb, min((j + 1) * nb, n)))
+            t, te = L[sl], E[sl]
+            assert np.array_equal(ff.round_to(t, int(m[i, j])), t), (i, j)
+            rel = np.linalg.norm(t - te) / np.linalg.norm(te)
+            worst = max(worst, rel)
+            assert rel <= u32, (i, j, rel)
+    print(f"split {split}: worst per-tile relative difference {worst:.2e} (u32 {u32:.2e})", flush=True)
+
