@@ -178,6 +178,7 @@ struct mpcr_factor {
   int* d_info = nullptr;
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles (the panel TRSM's FP64 workspace)
   double* d_dinv = nullptr;        // nt x nb x 32 doubles: inverted 32 x 32 diagonal blocks of every L_kk
+  uint16_t* d_split = nullptr;     // 2 x 3 (nt-1) nb^2 halfwords: split panels of the FP32 updates (step parity)
   double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles, each stored by rows
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   double* d_rpart = nullptr;       // partial products of the stored residual
@@ -273,7 +274,8 @@ void free_factor(mpcr_factor* f) {
   DeviceGuard g(f->device);
   for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
                   (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig, (void*)f->d_rpart, (void*)f->d_sc,
-                  (void*)f->d_pamax, (void*)f->d_tamax, (void*)f->d_ws8, (void*)f->d_amax8, (void*)f->d_dinv})
+                  (void*)f->d_pamax, (void*)f->d_tamax, (void*)f->d_ws8, (void*)f->d_amax8, (void*)f->d_dinv,
+                  (void*)f->d_split})
     dfree(f->arena, p);
   delete f;
 }
@@ -443,6 +445,13 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * nt), 0));
   static const int order[5] = {F64, F32, BF16, F16, F8};
   const int64_t nb2 = f->nb * f->nb;
+  // FP32 updates through the BF16 MFMA read split panels (two step parities)
+  bool any32 = false;
+  for (int64_t k = 0; k < nt; ++k) any32 |= f->task_cnt[k * 5 + F32] > 0;
+  const bool split32 = ctx->fp32_split && any32 && nt > 1;
+  const int64_t split_stride = 3 * (nt - 1) * nb2;
+  if (split32 && !f->d_split)
+    HIP_TRY(ctx, dmalloc(f->arena, &f->d_split, (size_t)(2 * split_stride) * sizeof(uint16_t)));
   // which: 0 = the SYRK of the next diagonal tile, 1 = the rest of the next
   // column, 2 = the columns after it
   auto launch_updates = [&](int64_t k, hipStream_t s, int which) -> int {
@@ -465,6 +474,9 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
         }));
       } else if (which == 0 && f->map[(k + 1) * nt + k] == F64) {
         HIP_TRY(ctx, timed(ctx, s, 10, fl, [&] { return launch_syrk_tile(tv, (int)k, (int)k + 1, s); }));
+      } else if (p == F32 && split32) {
+        const uint16_t* sp = f->d_split + (k & 1) * split_stride;
+        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update_f32_packed(tv, (int)k, t, cnt, sp, s); }));
       } else {
         HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s, ctx->fp32_split); }));
       }
@@ -481,6 +493,10 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
                        [&] { return launch_trsm_panel(tv, (int)k, f->d_trsm_ws, f->d_dinv + k * f->nb * 32, fp8_panel, P); }));
     if (f->task_cnt[k * 5 + F8] > 0)  // operand scales of the FP8 updates (buffer of this step's parity)
       HIP_TRY(ctx, launch_panel_amax(tv, (int)k, f->d_pamax + (k & 1) * nt, P));
+    // split panel of the FP32 updates (this step's parity: the buffer was last
+    // read by step k-2, whose updates P and C have waited for)
+    if (split32 && f->task_cnt[k * 5 + F32] > 0)
+      HIP_TRY(ctx, launch_pack_split(tv, (int)k, f->d_split + (k & 1) * split_stride, P));
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
     if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
     if ((rc = launch_updates(k, P, 0)) != MPCR_OK) return rc;
@@ -1021,6 +1037,7 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
   bytes += (size_t)std::max<int64_t>(nt - 1, 1) * tile;     // TRSM workspace
   bytes += (size_t)nt * nb * 32 * 8;                        // inverted 32 x 32 diagonal blocks
   bytes += (size_t)nt * tile;                               // inverted diagonal tiles
+  bytes += (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 12;  // split panels of the FP32 updates
   bytes += (size_t)solve_bytes(N, nrhs, n);                 // vectors
   bytes += (size_t)n * 24 + (size_t)nt * nt * 16 + 65536;   // sites, permutation, tables
   size_t npow2 = 1;

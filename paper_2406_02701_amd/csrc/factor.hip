@@ -600,6 +600,166 @@ __global__ __launch_bounds__(512) void k_update_f32_split(TileView tv, int k, co
       }
 }
 
+// Split panels: after the TRSM of step k, every panel tile (i, k) is converted
+// to FP32 and split once into its three BF16 planes, stored for the update
+// kernel in chunks of 32 k: plane p of panel tile q = i - k - 1 at
+//   out[(q * 3 + p) * nb^2 + (c * nb + row) * 32 + kk]   (k = 32 c + kk),
+// so a 128-row block of one chunk is 8 contiguous KB.  The FP32 updates of the
+// step then copy planes instead of splitting every operand in every block.
+__global__ __launch_bounds__(512) void k_pack_split(TileView tv, int k, uint16_t* out) {
+  const int nb = tv.nb, nch = nb / SBK, nrb = nb / UBM;
+  const int b = blockIdx.x;
+  const int q = b / (nch * nrb), c = (b / nrb) % nch, rb = b % nrb;
+  const int i = k + 1 + q;
+  const void* P = tv.tile(i, k);
+  const int f = tv.tfmt(i, k);
+  const double mul = tv.tmul(i, k);
+  const int mr = threadIdx.x & (UBM - 1), k0 = 8 * (threadIdx.x / UBM);
+  const int64_t row = (int64_t)rb * UBM + mr;
+  float v[8];
+  auto load = [&](auto tag) {
+    constexpr int SF = decltype(tag)::value;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = load1_f32<SF>(P, (int64_t)(SBK * c + k0 + e) * nb + row, mul);
+  };
+  switch (f) {
+    case F64: load(std::integral_constant<int, F64>{}); break;
+    case F32: load(std::integral_constant<int, F32>{}); break;
+    case F16: load(std::integral_constant<int, F16>{}); break;
+    case BF16: load(std::integral_constant<int, BF16>{}); break;
+    default: load(std::integral_constant<int, F8>{}); break;
+  }
+  u16x8 h, m, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint16_t a, bb, cc;
+    split3_bf16(v[e], a, bb, cc);
+    h[e] = a;
+    m[e] = bb;
+    l[e] = cc;
+  }
+  const int64_t nb2 = (int64_t)nb * nb;
+  uint16_t* o = out + (int64_t)q * 3 * nb2 + ((int64_t)c * nb + row) * SBK + k0;
+  *(u16x8*)o = h;
+  *(u16x8*)(o + nb2) = m;
+  *(u16x8*)(o + 2 * nb2) = l;
+}
+
+hipError_t launch_pack_split(const TileView& tv, int k, uint16_t* out, hipStream_t s) {
+  const int cnt = tv.nt - k - 1;
+  if (cnt <= 0) return hipSuccess;
+  k_pack_split<<<cnt * (tv.nb / SBK) * (tv.nb / UBM), 512, 0, s>>>(tv, k, out);
+  return hipGetLastError();
+}
+
+// FP32 updates from the split panels of step k (see k_pack_split): the same
+// products and staging as k_update_f32_split, the planes copied with 16-byte
+// loads (four lanes per row of a chunk).
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_update_f32_packed(TileView tv, int k, const GemmTask* tasks,
+                                                           const uint16_t* split) {
+  __shared__ __attribute__((aligned(16))) SplitBuf As;
+  __shared__ __attribute__((aligned(16))) SplitBuf Bs;
+
+  const int nb = tv.nb;
+  const int sub = nb / UBM;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int task = lb / (sub * sub);
+  const int blk = lb % (sub * sub);
+  const int bm = blk % sub, bn = blk / sub;
+  const GemmTask t = tasks[task];
+  if (t.i == t.j && bn > bm) return;
+  if (*tv.info) return;
+
+  const int64_t nb2 = (int64_t)nb * nb;
+  const uint16_t* Ap = split + (int64_t)(t.i - k - 1) * 3 * nb2;
+  const uint16_t* Bp = split + (int64_t)(t.j - k - 1) * 3 * nb2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
+  const int mr = tid >> 2, k0 = 8 * (tid & 3);
+
+  f4 acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f4{0, 0, 0, 0};
+
+  u16x8 ra[3], rb[3];
+  auto gload = [&](int kk) {
+    const int64_t c = kk / SBK;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      ra[p] = *(const u16x8*)(Ap + p * nb2 + (c * nb + arow0 + mr) * SBK + k0);
+      rb[p] = *(const u16x8*)(Bp + p * nb2 + (c * nb + brow0 + mr) * SBK + k0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      *(u16x8*)&As[p][mr][k0] = ra[p];
+      *(u16x8*)&Bs[p][mr][k0] = rb[p];
+    }
+  };
+  gload(0);
+  sstore();
+  __syncthreads();
+  const int kq8 = 8 * (lane >> 4);
+  for (int kk = 0; kk < nb; kk += SBK) {
+    const bool more = kk + SBK < nb;
+    if (more) gload(kk + SBK);
+    u16x8 a[3][4], b[3][2];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[p][x] = *(const u16x8*)&As[p][wm * 64 + x * 16 + (lane & 15)][kq8];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) b[p][y] = *(const u16x8*)&Bs[p][wn * 32 + y * 16 + (lane & 15)][kq8];
+    }
+#define MPCR_MF(PA, PB)                                                                                   \
+  acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[PA][x]),              \
+                                                      __builtin_bit_cast(bf16x8, b[PB][y]), acc[x][y], 0, 0, 0)
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        MPCR_MF(1, 1);
+        MPCR_MF(0, 2);
+        MPCR_MF(2, 0);
+        MPCR_MF(0, 1);
+        MPCR_MF(1, 0);
+        MPCR_MF(0, 0);
+      }
+#undef MPCR_MF
+    if (more) {
+      __syncthreads();
+      sstore();
+      __syncthreads();
+    }
+  }
+
+  void* Cp = tv.tile(t.i, t.j);
+  const bool diag = (t.i == t.j);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = arow0 + wm * 64 + x * 16 + 4 * (lane >> 4) + r;
+        const int64_t C = brow0 + wn * 32 + y * 16 + (lane & 15);
+        if (diag && C > R) continue;
+        rmw_sub<F32>(Cp, C * nb + R, (double)acc[x][y][r]);
+      }
+}
+
+hipError_t launch_tile_update_f32_packed(const TileView& tv, int k, const GemmTask* tasks, int ntasks,
+                                         const uint16_t* split, hipStream_t s) {
+  if (ntasks == 0) return hipSuccess;
+  const int sub = tv.nb / UBM;
+  k_update_f32_packed<<<ntasks * sub * sub, 512, 0, s>>>(tv, k, tasks, split);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Updates of FP8 output tiles (the update runs in the output tile's format):
 // both operands are converted to FP8 on load with the scale of their own tile
