@@ -653,10 +653,20 @@ hipError_t launch_pack_split(const TileView& tv, int k, uint16_t* out, hipStream
 }
 
 // FP32 updates from the split panels of step k (see k_pack_split): the same
-// products and staging as k_update_f32_split, the planes copied with 16-byte
-// loads (four lanes per row of a chunk).
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_update_f32_packed(TileView tv, int k, const GemmTask* tasks,
-                                                           const uint16_t* split) {
+// products as k_update_f32_split, the planes copied with 16-byte loads (four
+// per row of a chunk).  NW waves per 128 x 128 block: 8 waves of 64 x 32 or
+// 4 waves of 64 x 64; both run at the same rate in the factorisation (about
+// 112 TF/s FP32-equivalent at n = 32768), where the three planes (6 bytes per
+// operand element) make the operand stream, not the LDS or the MFMA, the limit.
+constexpr int SPLIT_WAVES = 8;
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2))) void
+k_update_f32_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* split) {
+  constexpr int NT = 64 * NW;
+  constexpr int WN = NW / 2;             // waves along n (2 along m)
+  constexpr int FY = (UBM / WN) / 16;    // 16-column MFMA tiles per wave along n
+  constexpr int G = 3 * UBM * 4 / NT;    // 16-byte vectors per thread per operand and chunk
   __shared__ __attribute__((aligned(16))) SplitBuf As;
   __shared__ __attribute__((aligned(16))) SplitBuf Bs;
 
@@ -676,28 +686,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
-  const int mr = tid >> 2, k0 = 8 * (tid & 3);
 
-  f4 acc[4][2];
+  f4 acc[4][FY];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = f4{0, 0, 0, 0};
+    for (int y = 0; y < FY; ++y) acc[x][y] = f4{0, 0, 0, 0};
 
-  u16x8 ra[3], rb[3];
+  // vector v = tid + NT g: plane v / 512, row (v % 512) / 4, k offset 8 (v % 4)
+  u16x8 ra[G], rb[G];
   auto gload = [&](int kk) {
     const int64_t c = kk / SBK;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      ra[p] = *(const u16x8*)(Ap + p * nb2 + (c * nb + arow0 + mr) * SBK + k0);
-      rb[p] = *(const u16x8*)(Bp + p * nb2 + (c * nb + brow0 + mr) * SBK + k0);
+    for (int g = 0; g < G; ++g) {
+      const int v = tid + NT * g, p = v / (UBM * 4), r = (v % (UBM * 4)) >> 2, k0 = 8 * (v & 3);
+      ra[g] = *(const u16x8*)(Ap + p * nb2 + (c * nb + arow0 + r) * SBK + k0);
+      rb[g] = *(const u16x8*)(Bp + p * nb2 + (c * nb + brow0 + r) * SBK + k0);
     }
   };
   auto sstore = [&]() {
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      *(u16x8*)&As[p][mr][k0] = ra[p];
-      *(u16x8*)&Bs[p][mr][k0] = rb[p];
+    for (int g = 0; g < G; ++g) {
+      const int v = tid + NT * g, p = v / (UBM * 4), r = (v % (UBM * 4)) >> 2, k0 = 8 * (v & 3);
+      *(u16x8*)&As[p][r][k0] = ra[g];
+      *(u16x8*)&Bs[p][r][k0] = rb[g];
     }
   };
   gload(0);
@@ -707,13 +719,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int kk = 0; kk < nb; kk += SBK) {
     const bool more = kk + SBK < nb;
     if (more) gload(kk + SBK);
-    u16x8 a[3][4], b[3][2];
+    u16x8 a[3][4], b[3][FY];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
 #pragma unroll
       for (int x = 0; x < 4; ++x) a[p][x] = *(const u16x8*)&As[p][wm * 64 + x * 16 + (lane & 15)][kq8];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) b[p][y] = *(const u16x8*)&Bs[p][wn * 32 + y * 16 + (lane & 15)][kq8];
+      for (int y = 0; y < FY; ++y) b[p][y] = *(const u16x8*)&Bs[p][wn * (16 * FY) + y * 16 + (lane & 15)][kq8];
     }
 #define MPCR_MF(PA, PB)                                                                                   \
   acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[PA][x]),              \
@@ -721,7 +733,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
+      for (int y = 0; y < FY; ++y) {
         MPCR_MF(1, 1);
         MPCR_MF(0, 2);
         MPCR_MF(2, 0);
@@ -742,11 +754,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < FY; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t R = arow0 + wm * 64 + x * 16 + 4 * (lane >> 4) + r;
-        const int64_t C = brow0 + wn * 32 + y * 16 + (lane & 15);
+        const int64_t C = brow0 + wn * (16 * FY) + y * 16 + (lane & 15);
         if (diag && C > R) continue;
         rmw_sub<F32>(Cp, C * nb + R, (double)acc[x][y][r]);
       }
@@ -756,7 +768,7 @@ hipError_t launch_tile_update_f32_packed(const TileView& tv, int k, const GemmTa
                                          const uint16_t* split, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
   const int sub = tv.nb / UBM;
-  k_update_f32_packed<<<ntasks * sub * sub, 512, 0, s>>>(tv, k, tasks, split);
+  k_update_f32_packed<SPLIT_WAVES><<<ntasks * sub * sub, 64 * SPLIT_WAVES, 0, s>>>(tv, k, tasks, split);
   return hipGetLastError();
 }
 
