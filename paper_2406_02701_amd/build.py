@@ -28,6 +28,8 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INCLUDE}",
 ]
+# roctx ranges (rocprofiler-sdk)
+LINK_FLAGS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 SOURCES = ["tiles.hip", "factor.hip", "solve.hip", "order.hip", "gemm.hip", "laplace.hip", "mala.hip", "krylov.hip", "api.cpp", "serve.cpp"]
 
 
@@ -50,7 +52,7 @@ def build(jobs: int = 8) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LINK_FLAGS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -485,6 +485,7 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   };
   int rc;
   for (int64_t k = 0; k < nt; ++k) {
+    TraceRange step("tile step");
     bool fp8_panel = false;
     for (int64_t i = k + 1; i < nt; ++i) fp8_panel |= (f->map[i * nt + k] == F8);
     HIP_TRY(ctx, timed(ctx, P, 5, nb3 / 3.0, [&] { return launch_potrf_tile(tv, (int)k, f->d_dinv + k * f->nb * 32, P); }));
@@ -656,6 +657,7 @@ int krylov_ws(mpcr_ctx* ctx, int64_t bytes, char** out) {
 // b.B / b.X (padded N x nrhs).
 int refine(mpcr_ctx* ctx, mpcr_factor* f, SolveBufs& b, const SigmaOp& op, const mpcr_refine_opts_t& o,
            mpcr_diag_t* diag, bool* converged_out) {
+  TraceRange tr("refinement");
   hipStream_t s = ctx->stream;
   const int n = (int)f->n, nrhs = (int)b.nrhs;
   const int64_t ld = b.N;
@@ -1346,6 +1348,7 @@ int mpcr_covariance_tile_amax(mpcr_ctx* ctx, int64_t n, int64_t nb, const double
 
 int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda, const mpcr_tilemap_t* map,
                      mpcr_factor** out, int64_t* h_info) {
+  TraceRange tr("mpcr_potrf_tiled");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   CHECK_ARG(ctx, out != nullptr, "out is NULL");
   *out = nullptr;
@@ -1370,6 +1373,7 @@ int mpcr_potrf_tiled(mpcr_ctx* ctx, int64_t n, const double* d_A, int64_t lda, c
 
 int mpcr_potrf_tiled_covariance(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_theta_t* theta,
                                 const mpcr_tilemap_t* map, mpcr_factor** out, int64_t* h_info) {
+  TraceRange tr("mpcr_potrf_tiled_covariance");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   CHECK_ARG(ctx, out != nullptr, "out is NULL");
   *out = nullptr;
@@ -1451,6 +1455,7 @@ int mpcr_trsm_forward(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const 
 
 int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double* d_B, int64_t ldb, double* d_X,
                int64_t ldx, const double* d_A_fp64, int64_t lda, const mpcr_refine_opts_t* opts, mpcr_diag_t* diag) {
+  TraceRange tr("mpcr_potrs");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   CHECK_ARG(ctx, fc != nullptr, "factor is NULL");
   CHECK_ARG(ctx, fc->info == 0, "factor is not positive definite");
@@ -1493,6 +1498,7 @@ int mpcr_potrs(mpcr_ctx* ctx, const mpcr_factor* fc, int64_t nrhs, const double*
 int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_Z, int64_t nrhs,
                       const mpcr_theta_t* theta, const mpcr_tilemap_t* map, int order, const mpcr_refine_opts_t* opts,
                       double* h_loglik, mpcr_diag_t* diag) {
+  TraceRange tr("mpcr_gauss_loglik");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   int rc = check_theta(ctx, theta);
   if (rc) return rc;
@@ -1591,9 +1597,12 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
     }
     HIP_TRY(ctx, launch_tiles_from_covariance(f->view(), locs, *theta, s, stored_residual ? f->d_sig : nullptr));
     if (promotions == 0) HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
-    if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    rc = read_info(ctx, f, &info);
+    {
+      TraceRange tr("factorisation");
+      if ((rc = run_factorisation(ctx, f)) != MPCR_OK) return rc;
+      HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+      rc = read_info(ctx, f, &info);  // synchronises: the range spans the factorisation's GPU work
+    }
     if (rc != MPCR_ERR_NOT_SPD || !promote || promotions >= 8) break;
     std::vector<uint8_t> m2 = ctx->ws_map;
     if (!promote_map(m2, nt, nb, info)) break;
@@ -1689,6 +1698,7 @@ int mpcr_gauss_loglik(mpcr_ctx* ctx, int64_t n, const double* d_locs, const doub
 int mpcr_mle_fit(mpcr_ctx* ctx, int64_t n, const double* d_locs, const double* d_z, double nu, double nugget,
                  const mpcr_tilemap_t* map, const mpcr_refine_opts_t* refine, const double* h_x0, int max_iter,
                  double reltol, double* h_x_out, double* h_nll_out, int* h_iters, int* h_evals) {
+  TraceRange tr("mpcr_mle_fit");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs && d_z && h_x0 && h_x_out && h_nll_out, "bad arguments");
   CHECK_ARG(ctx, nu == 0.5 || nu == 1.5 || nu == 2.5, "nu must be 0.5, 1.5 or 2.5");
@@ -1815,6 +1825,7 @@ int mpcr_inla_posterior(mpcr_ctx* ctx, int64_t n, const double* d_locs, const do
                         double beta, const double* h_range, int nrange, double newton_tol, int max_newton,
                         const mpcr_tilemap_t* map, double* h_lpost, double* h_posterior, int* h_newton_iters,
                         double* d_mode_out) {
+  TraceRange tr("mpcr_inla_posterior");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   CHECK_ARG(ctx, n > 0 && n < (1ll << 31) && d_locs && d_y && h_range && h_lpost, "bad arguments");
   CHECK_ARG(ctx, nu == 0.5 || nu == 1.5 || nu == 2.5, "nu must be 0.5, 1.5 or 2.5");
@@ -1877,6 +1888,7 @@ int mpcr_mala_run(mpcr_ctx* ctx, int64_t n, const double* d_locs, const mpcr_the
                   const mpcr_theta_t* precond, double h, const double* d_z0, int iters, const double* d_eps,
                   const double* h_unif, const mpcr_tilemap_t* map, double* d_z_out, double* d_trace,
                   int* h_accepted, double* h_log_ratio) {
+  TraceRange tr("mpcr_mala_run");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   int rc = check_theta(ctx, target);
   if (rc) return rc;
@@ -2039,6 +2051,7 @@ int mpcr_convert(mpcr_ctx* ctx, mpcr_prec_t prec, int64_t m, int64_t n, const do
 int mpcr_gemm(mpcr_ctx* ctx, mpcr_prec_t prec, int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha,
               const void* d_A, int64_t lda, const int8_t* d_scaleA_exp, const void* d_B, int64_t ldb,
               const int8_t* d_scaleB_exp, double beta, void* d_C, int64_t ldc, mpcr_prec_t c_prec) {
+  TraceRange tr("mpcr_gemm");
   CHECK_ARG(ctx, ctx != nullptr, "NULL context");
   const int p = (int)prec, cp = (int)c_prec;
   CHECK_ARG(ctx, valid_prec(p) && (cp == F64 || cp == F32), "bad formats");

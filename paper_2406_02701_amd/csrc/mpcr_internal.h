@@ -14,8 +14,20 @@
 #include <stdint.h>
 
 #include "../../include/mpcr.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 namespace mpcr {
+
+// Host-side trace range (rocprofv3 --marker-trace): spans the queueing of a
+// call or phase; with a synchronisation inside the phase it also spans its GPU
+// work.  The kernels themselves appear in the kernel trace.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 
 enum Fmt : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, F8 = 4 };
 

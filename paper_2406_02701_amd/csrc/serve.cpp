@@ -88,6 +88,7 @@ int request_map(mpcr_ctx* ctx, const mpcr_serve_opts_t& o, int64_t n, const doub
 
 // One request on the worker's context: Morton order, map, log-likelihood.
 void run_request(mpcr_server* srv, mpcr_ctx* ctx, Request& r, Done& d) {
+  TraceRange tr("serve request");
   const mpcr_serve_opts_t& o = srv->opts;
   hipStream_t s = ctx_stream(ctx);
   const int64_t n = r.n;
