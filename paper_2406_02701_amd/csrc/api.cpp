@@ -179,6 +179,7 @@ struct mpcr_factor {
   double* d_trsm_ws = nullptr;     // (nt-1) nb^2 doubles (the panel TRSM's FP64 workspace)
   double* d_dinv = nullptr;        // nt x nb x 32 doubles: inverted 32 x 32 diagonal blocks of every L_kk
   uint16_t* d_split = nullptr;     // 2 x 3 (nt-1) nb^2 halfwords: split panels of the FP32 updates (step parity)
+  uint16_t* d_b16 = nullptr;       // 2 x (nt-1) nb^2 halfwords: BF16 panels of the BF16 updates (step parity)
   double* d_Linv = nullptr;        // nt nb^2 doubles: the inverted diagonal tiles, each stored by rows
   double* d_sig = nullptr;         // optional FP64 copy of Sigma's lower tiles (stored residual)
   double* d_rpart = nullptr;       // partial products of the stored residual
@@ -275,7 +276,7 @@ void free_factor(mpcr_factor* f) {
   for (void* p : {(void*)f->d_base, (void*)f->d_off, (void*)f->d_fmt, (void*)f->d_info, (void*)f->d_trsm_ws,
                   (void*)f->d_Linv, (void*)f->d_tasks, (void*)f->d_sig, (void*)f->d_rpart, (void*)f->d_sc,
                   (void*)f->d_pamax, (void*)f->d_tamax, (void*)f->d_ws8, (void*)f->d_amax8, (void*)f->d_dinv,
-                  (void*)f->d_split})
+                  (void*)f->d_split, (void*)f->d_b16})
     dfree(f->arena, p);
   delete f;
 }
@@ -452,6 +453,13 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   const int64_t split_stride = 3 * (nt - 1) * nb2;
   if (split32 && !f->d_split)
     HIP_TRY(ctx, dmalloc(f->arena, &f->d_split, (size_t)(2 * split_stride) * sizeof(uint16_t)));
+  // BF16 updates read their operands from BF16 panels packed the same way
+  bool any16 = false;
+  for (int64_t k = 0; k < nt; ++k) any16 |= f->task_cnt[k * 5 + BF16] > 0;
+  const bool pack16 = any16 && nt > 1;
+  const int64_t b16_stride = (nt - 1) * nb2;
+  if (pack16 && !f->d_b16)
+    HIP_TRY(ctx, dmalloc(f->arena, &f->d_b16, (size_t)(2 * b16_stride) * sizeof(uint16_t)));
   // which: 0 = the SYRK of the next diagonal tile, 1 = the rest of the next
   // column, 2 = the columns after it
   auto launch_updates = [&](int64_t k, hipStream_t s, int which) -> int {
@@ -474,9 +482,9 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
         }));
       } else if (which == 0 && f->map[(k + 1) * nt + k] == F64) {
         HIP_TRY(ctx, timed(ctx, s, 10, fl, [&] { return launch_syrk_tile(tv, (int)k, (int)k + 1, s); }));
-      } else if (p == F32 && split32) {
-        const uint16_t* sp = f->d_split + (k & 1) * split_stride;
-        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update_f32_packed(tv, (int)k, t, cnt, sp, s); }));
+      } else if ((p == F32 && split32) || (p == BF16 && pack16)) {
+        const uint16_t* sp = p == F32 ? f->d_split + (k & 1) * split_stride : f->d_b16 + (k & 1) * b16_stride;
+        HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update_packed(tv, (int)k, p, t, cnt, sp, s); }));
       } else {
         HIP_TRY(ctx, timed(ctx, s, p, fl, [&] { return launch_tile_update(tv, (int)k, p, t, cnt, s, ctx->fp32_split); }));
       }
@@ -496,8 +504,11 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
       HIP_TRY(ctx, launch_panel_amax(tv, (int)k, f->d_pamax + (k & 1) * nt, P));
     // split panel of the FP32 updates (this step's parity: the buffer was last
     // read by step k-2, whose updates P and C have waited for)
-    if (split32 && f->task_cnt[k * 5 + F32] > 0)
-      HIP_TRY(ctx, launch_pack_split(tv, (int)k, f->d_split + (k & 1) * split_stride, P));
+    {
+      uint16_t* o3 = (split32 && f->task_cnt[k * 5 + F32] > 0) ? f->d_split + (k & 1) * split_stride : nullptr;
+      uint16_t* ob = (pack16 && f->task_cnt[k * 5 + BF16] > 0) ? f->d_b16 + (k & 1) * b16_stride : nullptr;
+      HIP_TRY(ctx, launch_pack_split(tv, (int)k, o3, ob, P));
+    }
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
     if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
     if ((rc = launch_updates(k, P, 0)) != MPCR_OK) return rc;
@@ -1039,7 +1050,7 @@ size_t loglik_footprint(int64_t n, int64_t nb, int64_t nrhs) {
   bytes += (size_t)std::max<int64_t>(nt - 1, 1) * tile;     // TRSM workspace
   bytes += (size_t)nt * nb * 32 * 8;                        // inverted 32 x 32 diagonal blocks
   bytes += (size_t)nt * tile;                               // inverted diagonal tiles
-  bytes += (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 12;  // split panels of the FP32 updates
+  bytes += (size_t)std::max<int64_t>(nt - 1, 1) * nb * nb * 16;  // split FP32 and BF16 panels of the updates
   bytes += (size_t)solve_bytes(N, nrhs, n);                 // vectors
   bytes += (size_t)n * 24 + (size_t)nt * nt * 16 + 65536;   // sites, permutation, tables
   size_t npow2 = 1;

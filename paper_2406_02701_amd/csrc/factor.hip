@@ -603,10 +603,21 @@ __global__ __launch_bounds__(512) void k_update_f32_split(TileView tv, int k, co
 // Split panels: after the TRSM of step k, every panel tile (i, k) is converted
 // to FP32 and split once into its three BF16 planes, stored for the update
 // kernel in chunks of 32 k: plane p of panel tile q = i - k - 1 at
-//   out[(q * 3 + p) * nb^2 + (c * nb + row) * 32 + kk]   (k = 32 c + kk),
+//   out3[(q * 3 + p) * nb^2 + (c * nb + row) * 32 + kk]   (k = 32 c + kk),
 // so a 128-row block of one chunk is 8 contiguous KB.  The FP32 updates of the
 // step then copy planes instead of splitting every operand in every block.
-__global__ __launch_bounds__(512) void k_pack_split(TileView tv, int k, uint16_t* out) {
+// outb (when not NULL) receives, in the same layout, each element rounded once
+// to BF16 from its stored format: the operands of the step's BF16 updates.
+template <int SF>
+__device__ __forceinline__ uint16_t load1_bf16(const void* p, int64_t idx, double mul) {
+  if constexpr (SF == BF16) return ((const uint16_t*)p)[idx];
+  else if constexpr (SF == F32) return f32_to_bf16_rne(((const float*)p)[idx]);
+  else if constexpr (SF == F64) return to_bf16(((const double*)p)[idx]);
+  else if constexpr (SF == F16) return to_bf16((double)f16_to_f32(((const uint16_t*)p)[idx]));
+  else return to_bf16((double)e4m3_to_f32(((const uint8_t*)p)[idx]) * mul);
+}
+
+__global__ __launch_bounds__(512) void k_pack_split(TileView tv, int k, uint16_t* out3, uint16_t* outb) {
   const int nb = tv.nb, nch = nb / SBK, nrb = nb / UBM;
   const int b = blockIdx.x;
   const int q = b / (nch * nrb), c = (b / nrb) % nch, rb = b % nrb;
@@ -616,11 +627,18 @@ __global__ __launch_bounds__(512) void k_pack_split(TileView tv, int k, uint16_t
   const double mul = tv.tmul(i, k);
   const int mr = threadIdx.x & (UBM - 1), k0 = 8 * (threadIdx.x / UBM);
   const int64_t row = (int64_t)rb * UBM + mr;
+  const int64_t nb2 = (int64_t)nb * nb;
+  const int64_t at = ((int64_t)c * nb + row) * SBK + k0;
   float v[8];
+  u16x8 bv;
   auto load = [&](auto tag) {
     constexpr int SF = decltype(tag)::value;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = load1_f32<SF>(P, (int64_t)(SBK * c + k0 + e) * nb + row, mul);
+    for (int e = 0; e < 8; ++e) {
+      const int64_t idx = (int64_t)(SBK * c + k0 + e) * nb + row;
+      if (out3) v[e] = load1_f32<SF>(P, idx, mul);
+      if (outb) bv[e] = load1_bf16<SF>(P, idx, mul);
+    }
   };
   switch (f) {
     case F64: load(std::integral_constant<int, F64>{}); break;
@@ -629,46 +647,51 @@ __global__ __launch_bounds__(512) void k_pack_split(TileView tv, int k, uint16_t
     case BF16: load(std::integral_constant<int, BF16>{}); break;
     default: load(std::integral_constant<int, F8>{}); break;
   }
-  u16x8 h, m, l;
+  if (outb) *(u16x8*)(outb + (int64_t)q * nb2 + at) = bv;
+  if (out3) {
+    u16x8 h, m, l;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    uint16_t a, bb, cc;
-    split3_bf16(v[e], a, bb, cc);
-    h[e] = a;
-    m[e] = bb;
-    l[e] = cc;
+    for (int e = 0; e < 8; ++e) {
+      uint16_t a, bb, cc;
+      split3_bf16(v[e], a, bb, cc);
+      h[e] = a;
+      m[e] = bb;
+      l[e] = cc;
+    }
+    uint16_t* o = out3 + (int64_t)q * 3 * nb2 + at;
+    *(u16x8*)o = h;
+    *(u16x8*)(o + nb2) = m;
+    *(u16x8*)(o + 2 * nb2) = l;
   }
-  const int64_t nb2 = (int64_t)nb * nb;
-  uint16_t* o = out + (int64_t)q * 3 * nb2 + ((int64_t)c * nb + row) * SBK + k0;
-  *(u16x8*)o = h;
-  *(u16x8*)(o + nb2) = m;
-  *(u16x8*)(o + 2 * nb2) = l;
 }
 
-hipError_t launch_pack_split(const TileView& tv, int k, uint16_t* out, hipStream_t s) {
+hipError_t launch_pack_split(const TileView& tv, int k, uint16_t* out3, uint16_t* outb, hipStream_t s) {
   const int cnt = tv.nt - k - 1;
-  if (cnt <= 0) return hipSuccess;
-  k_pack_split<<<cnt * (tv.nb / SBK) * (tv.nb / UBM), 512, 0, s>>>(tv, k, out);
+  if (cnt <= 0 || (!out3 && !outb)) return hipSuccess;
+  k_pack_split<<<cnt * (tv.nb / SBK) * (tv.nb / UBM), 512, 0, s>>>(tv, k, out3, outb);
   return hipGetLastError();
 }
 
-// FP32 updates from the split panels of step k (see k_pack_split): the same
-// products as k_update_f32_split, the planes copied with 16-byte loads (four
-// per row of a chunk).  NW waves per 128 x 128 block: 8 waves of 64 x 32 or
+// Updates from the packed panels of step k (see k_pack_split), planes copied
+// with 16-byte loads (four per row of a chunk).  NPL = 3: FP32 output tiles,
+// the six split products of k_update_f32_split; NPL = 1: BF16 output tiles,
+// one BF16 product per fragment pair on operands rounded once to BF16 (the
+// same k order of MFMAs as k_update_mmajor<BF16>, so the same results).  NW waves per 128 x 128 block: 8 waves of 64 x 32 or
 // 4 waves of 64 x 64; both run at the same rate in the factorisation (about
 // 112 TF/s FP32-equivalent at n = 32768), where the three planes (6 bytes per
 // operand element) make the operand stream, not the LDS or the MFMA, the limit.
 constexpr int SPLIT_WAVES = 8;
 
-template <int NW>
+template <int NW, int NPL>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2))) void
-k_update_f32_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* split) {
+k_update_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* split) {
   constexpr int NT = 64 * NW;
   constexpr int WN = NW / 2;             // waves along n (2 along m)
   constexpr int FY = (UBM / WN) / 16;    // 16-column MFMA tiles per wave along n
-  constexpr int G = 3 * UBM * 4 / NT;    // 16-byte vectors per thread per operand and chunk
-  __shared__ __attribute__((aligned(16))) SplitBuf As;
-  __shared__ __attribute__((aligned(16))) SplitBuf Bs;
+  constexpr int G = NPL * UBM * 4 / NT;  // 16-byte vectors per thread per operand and chunk
+  constexpr int CF = NPL == 3 ? F32 : BF16;
+  __shared__ __attribute__((aligned(16))) uint16_t As[NPL][UBM][SLDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[NPL][UBM][SLDK];
 
   const int nb = tv.nb;
   const int sub = nb / UBM;
@@ -681,8 +704,8 @@ k_update_f32_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* s
   if (*tv.info) return;
 
   const int64_t nb2 = (int64_t)nb * nb;
-  const uint16_t* Ap = split + (int64_t)(t.i - k - 1) * 3 * nb2;
-  const uint16_t* Bp = split + (int64_t)(t.j - k - 1) * 3 * nb2;
+  const uint16_t* Ap = split + (int64_t)(t.i - k - 1) * NPL * nb2;
+  const uint16_t* Bp = split + (int64_t)(t.j - k - 1) * NPL * nb2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int64_t arow0 = (int64_t)bm * UBM, brow0 = (int64_t)bn * UBM;
@@ -719,9 +742,9 @@ k_update_f32_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* s
   for (int kk = 0; kk < nb; kk += SBK) {
     const bool more = kk + SBK < nb;
     if (more) gload(kk + SBK);
-    u16x8 a[3][4], b[3][FY];
+    u16x8 a[NPL][4], b[NPL][FY];
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < NPL; ++p) {
 #pragma unroll
       for (int x = 0; x < 4; ++x) a[p][x] = *(const u16x8*)&As[p][wm * 64 + x * 16 + (lane & 15)][kq8];
 #pragma unroll
@@ -734,11 +757,13 @@ k_update_f32_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* s
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int y = 0; y < FY; ++y) {
-        MPCR_MF(1, 1);
-        MPCR_MF(0, 2);
-        MPCR_MF(2, 0);
-        MPCR_MF(0, 1);
-        MPCR_MF(1, 0);
+        if constexpr (NPL == 3) {
+          MPCR_MF(1, 1);
+          MPCR_MF(0, 2);
+          MPCR_MF(2, 0);
+          MPCR_MF(0, 1);
+          MPCR_MF(1, 0);
+        }
         MPCR_MF(0, 0);
       }
 #undef MPCR_MF
@@ -760,15 +785,20 @@ k_update_f32_packed(TileView tv, int k, const GemmTask* tasks, const uint16_t* s
         const int64_t R = arow0 + wm * 64 + x * 16 + 4 * (lane >> 4) + r;
         const int64_t C = brow0 + wn * (16 * FY) + y * 16 + (lane & 15);
         if (diag && C > R) continue;
-        rmw_sub<F32>(Cp, C * nb + R, (double)acc[x][y][r]);
+        rmw_sub<CF>(Cp, C * nb + R, (double)acc[x][y][r]);
       }
 }
 
-hipError_t launch_tile_update_f32_packed(const TileView& tv, int k, const GemmTask* tasks, int ntasks,
-                                         const uint16_t* split, hipStream_t s) {
+hipError_t launch_tile_update_packed(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
+                                     const uint16_t* planes, hipStream_t s) {
   if (ntasks == 0) return hipSuccess;
   const int sub = tv.nb / UBM;
-  k_update_f32_packed<SPLIT_WAVES><<<ntasks * sub * sub, 64 * SPLIT_WAVES, 0, s>>>(tv, k, tasks, split);
+  if (cfmt == F32)
+    k_update_packed<SPLIT_WAVES, 3><<<ntasks * sub * sub, 64 * SPLIT_WAVES, 0, s>>>(tv, k, tasks, planes);
+  else if (cfmt == BF16)
+    k_update_packed<8, 1><<<ntasks * sub * sub, 512, 0, s>>>(tv, k, tasks, planes);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

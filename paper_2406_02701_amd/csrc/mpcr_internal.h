@@ -248,12 +248,14 @@ hipError_t launch_tile_update_fp8(const TileView& tv, int k, const GemmTask* tas
                                   float* ws32, unsigned* amax32, hipStream_t s);
 hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, const double* dinv, bool fp8_panel,
                              hipStream_t s);
-// split panels for the FP32 updates of step k: every panel tile (i, k), i > k,
-// converted to FP32 and split into three BF16 planes (3 (nt-k-1) nb^2 halfwords)
-hipError_t launch_pack_split(const TileView& tv, int k, uint16_t* out, hipStream_t s);
-// FP32 tile updates of step k from those planes (BF16 MFMA, six products)
-hipError_t launch_tile_update_f32_packed(const TileView& tv, int k, const GemmTask* tasks, int ntasks,
-                                         const uint16_t* split, hipStream_t s);
+// packed panels of step k: every panel tile (i, k), i > k, converted to FP32
+// and split into three BF16 planes (out3: 3 (nt-k-1) nb^2 halfwords) and/or
+// rounded once to BF16 (outb: (nt-k-1) nb^2 halfwords); either may be NULL
+hipError_t launch_pack_split(const TileView& tv, int k, uint16_t* out3, uint16_t* outb, hipStream_t s);
+// tile updates of step k from those planes: cfmt F32 (three planes, six BF16
+// products) or BF16 (one plane)
+hipError_t launch_tile_update_packed(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
+                                     const uint16_t* planes, hipStream_t s);
 // fp32_split: FP32 output tiles through the BF16 MFMA with operands split
 // into three BF16 parts (FP32-level accuracy); else the FP32 MFMA
 hipError_t launch_tile_update(const TileView& tv, int k, int cfmt, const GemmTask* tasks, int ntasks,
