@@ -602,7 +602,9 @@ def main():
     # the trailing updates share the GPU with the next-column and POTRF/TRSM
     # streams, so a launch's duration includes some sharing; the FP64 path's
     # figure is given beside it
-    roofline["overlap"] = "launches share the GPU with the next-column update and POTRF/TRSM streams"
+    roofline["overlap"] = ("launches share the GPU: FP64 and lower-format updates run on two concurrent streams, "
+                           "beside the next-column update and POTRF/TRSM streams; a launch's duration includes that "
+                           "sharing (profiles/mfma_utilisation_n32768.md has each kernel alone)")
     roofline_fp64_path = roof(kstats64, 0, None)
 
     fl_by = list(d_mix.flops_by_prec)

@@ -109,6 +109,7 @@ struct mpcr_ctx {
   // lookahead: a second stream for the bulk of each trailing update
   hipStream_t upd = nullptr;        // trailing updates of the factorisation
   hipStream_t col = nullptr;        // updates of the next panel column
+  hipStream_t upd2 = nullptr;       // trailing updates of the tiles below FP64 (FP32, 16-bit, FP8)
   std::vector<hipEvent_t> sync_ev;  // timing-disabled events, 3 per step
 };
 
@@ -151,8 +152,8 @@ hipError_t timed(mpcr_ctx* ctx, hipStream_t s, int kind, double flops, F&& launc
 }
 
 hipError_t ensure_lookahead(mpcr_ctx* ctx, size_t nev, bool need_col) {
-  for (hipStream_t* st : {&ctx->upd, &ctx->col})
-    if (!*st && (st != &ctx->col || need_col)) {
+  for (hipStream_t* st : {&ctx->upd, &ctx->col, &ctx->upd2})
+    if (!*st && (st == &ctx->upd || need_col)) {
       hipError_t e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
       if (e != hipSuccess) return e;
     }
@@ -436,14 +437,19 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
   // hide POTRF(k+1) behind; small factorisations (serving) keep the next
   // column on P, which then runs POTRF(k), TRSM(k) and the whole column k+1
   const bool use_col = nt > COL_STREAM_MIN_NT;
-  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(3 * nt + 2), use_col));
-  hipStream_t U = ctx->upd, C = use_col ? ctx->col : P;
+  HIP_TRY(ctx, ensure_lookahead(ctx, (size_t)(4 * nt + 2), use_col));
+  // the trailing updates of step k go to U (FP64 tiles) and U2 (the other
+  // formats): a tile has one format, so the two streams never write the same
+  // tile, and their launches fill each other's tails
+  hipStream_t U = ctx->upd, C = use_col ? ctx->col : P, U2 = use_col ? ctx->upd2 : ctx->upd;
   auto ev = [&](int64_t i) { return ctx->sync_ev[i]; };      // 2k: TRSM(k) done (P), 2k+1: U's step k done
   auto evc = [&](int64_t k) { return ctx->sync_ev[2 * nt + 2 + k]; };  // C's column k+1 done
-  // U and C start after everything queued on P so far (the tile fill)
+  auto ev2 = [&](int64_t k) { return ctx->sync_ev[3 * nt + 2 + k]; };  // U2's step k done
+  // U, U2 and C start after everything queued on P so far (the tile fill)
   HIP_TRY(ctx, hipEventRecord(ev(2 * nt), P));
   HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * nt), 0));
   HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * nt), 0));
+  if (U2 != U) HIP_TRY(ctx, hipStreamWaitEvent(U2, ev(2 * nt), 0));
   static const int order[5] = {F64, F32, BF16, F16, F8};
   const int64_t nb2 = f->nb * f->nb;
   // FP32 updates through the BF16 MFMA read split panels (two step parities)
@@ -462,8 +468,9 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
     HIP_TRY(ctx, dmalloc(f->arena, &f->d_b16, (size_t)(2 * b16_stride) * sizeof(uint16_t)));
   // which: 0 = the SYRK of the next diagonal tile, 1 = the rest of the next
   // column, 2 = the columns after it
-  auto launch_updates = [&](int64_t k, hipStream_t s, int which) -> int {
+  auto launch_updates = [&](int64_t k, hipStream_t s0, int which) -> int {
     for (int p : order) {
+      const hipStream_t s = (which == 2 && p != F64) ? U2 : s0;
       const int all = f->task_cnt[k * 5 + p], nx = f->task_cnt_next[k * 5 + p];
       // the next column's tasks come first, its diagonal tile (FP64) first among them
       const int nd = (p == F64 && nx > 0) ? 1 : 0;
@@ -510,17 +517,26 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
       HIP_TRY(ctx, launch_pack_split(tv, (int)k, o3, ob, P));
     }
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
-    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));  // U finished step k-1
+    if (k > 0) {  // U and U2 finished step k-1
+      HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));
+      HIP_TRY(ctx, hipStreamWaitEvent(P, ev2(k - 1), 0));
+    }
     if ((rc = launch_updates(k, P, 0)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * k), 0));
-    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * (k - 1) + 1), 0));
+    if (k > 0) {
+      HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * (k - 1) + 1), 0));
+      HIP_TRY(ctx, hipStreamWaitEvent(C, ev2(k - 1), 0));
+    }
     if ((rc = launch_updates(k, C, 1)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipEventRecord(evc(k), C));
     HIP_TRY(ctx, hipStreamWaitEvent(U, ev(2 * k), 0));
+    if (U2 != U) HIP_TRY(ctx, hipStreamWaitEvent(U2, ev(2 * k), 0));
     if ((rc = launch_updates(k, U, 2)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipEventRecord(ev(2 * k + 1), U));
+    HIP_TRY(ctx, hipEventRecord(ev2(k), U2));
   }
   HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * nt - 1), 0));  // join
+  HIP_TRY(ctx, hipStreamWaitEvent(P, ev2(nt - 1), 0));
   HIP_TRY(ctx, hipStreamWaitEvent(P, evc(nt - 1), 0));
   return MPCR_OK;
 }
@@ -1183,6 +1199,7 @@ int mpcr_ctx_destroy(mpcr_ctx* ctx) {
     for (auto& e : ctx->sync_ev) (void)hipEventDestroy(e);
     if (ctx->upd) (void)hipStreamDestroy(ctx->upd);
     if (ctx->col) (void)hipStreamDestroy(ctx->col);
+    if (ctx->upd2) (void)hipStreamDestroy(ctx->upd2);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
