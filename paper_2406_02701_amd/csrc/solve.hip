@@ -40,24 +40,77 @@ constexpr int SW = 8;  // waves per workgroup of the tile products (each nb / SW
 constexpr int STHREADS = 64 * SW;
 constexpr int SW4 = 8;  // waves per workgroup of the wide update products
 
+// Raw storage element of a tile format and its widening to FP64: the wide
+// update loop holds its prefetched tile values in the storage width and widens
+// them at the MFMA, which keeps the narrow formats' register footprint small.
+template <int F> struct RawOf { using T = double; };
+template <> struct RawOf<F32> { using T = float; };
+template <> struct RawOf<F16> { using T = uint16_t; };
+template <> struct RawOf<BF16> { using T = uint16_t; };
+template <> struct RawOf<F8> { using T = uint8_t; };
+template <int F>
+__device__ __forceinline__ typename RawOf<F>::T ldraw(const void* p, int64_t i) {
+  return ((const typename RawOf<F>::T*)p)[i];
+}
+template <int F>
+__device__ __forceinline__ double widen(typename RawOf<F>::T v, double mul) {
+  if constexpr (F == F64) return v;
+  else if constexpr (F == F32) return (double)v;
+  else if constexpr (F == F16) return (double)f16_to_f32(v);
+  else if constexpr (F == BF16) return (double)bf16_to_f32(v);
+  else return (double)e4m3_to_f32(v) * mul;  // FP8 tiles hold codes of v 2^s
+}
+
+// N consecutive stored elements M[idx .. idx+N) with one vector load (idx a
+// multiple of N).
+template <int F, int N>
+__device__ __forceinline__ void ldrow(const void* M, int64_t idx, typename RawOf<F>::T (&out)[N]) {
+  using RT = typename RawOf<F>::T;
+  typedef RT VT __attribute__((ext_vector_type(N)));
+  const VT v = *(const VT*)((const RT*)M + idx);
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = v[i];
+}
+
 // acc0/acc1 += op(M)[row, k0 .. k1) * V[k0 .. k1, c], op(M)[row][k] = M[k * ldm + row]
 // (TRANS false) or M[row * ldm + k] (TRANS true); V is this lane's column of
-// the right-hand side (element k at V[k * vsk]; NULL: zero).  k1 - k0 is a
-// multiple of 4; the k4 steps of a batch past k1 read nothing and multiply
-// zeros.
+// the right-hand side (element k at V[k * vsk]; NULL: zero).  k0 and k1 are
+// multiples of 16; the k4 steps of a batch past k1 read nothing and multiply
+// zeros.  Which k a lane group supplies at which k4 step is free (A and B
+// agree): TRANS false, group q takes k = kk + 4u + q at step u (the 16 lanes
+// of a group read 16 consecutive rows of a column); TRANS true with FP64
+// tiles (the inverted diagonal tiles), group q takes the runs of four k from
+// kk + 4q and kk + 16 + 4q (each lane reads a run of its row with one vector
+// load); the other formats of the short update launches keep the first order,
+// which holds their loop within 128 VGPRs.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span(const void* M, int64_t ldm, int64_t row, int k0, int k1, const double* V,
                                           int64_t vsk, int lane, d4& acc0, d4& acc1, double mul = 1.0) {
   const int q = lane >> 4;
   double a[MB], b[MB], an[MB], bn[MB];
   auto load = [&](int kk, double* da, double* db) {
+    if constexpr (TRANS && F == F64) {
 #pragma unroll
-    for (int u = 0; u < MB; ++u) {
-      const int64_t k = kk + 4 * u + q;
-      const bool in = kk + 4 * u < k1;
-      da[u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
-      if constexpr (F == F8) da[u] *= mul;  // FP8 tiles hold codes of v 2^s
-      db[u] = (V && in) ? V[k * vsk] : 0.0;
+      for (int g = 0; g < MB / 4; ++g) {
+        const int64_t kb = kk + 16 * g + 4 * q;
+        const bool in = kk + 16 * g < k1;
+        typename RawOf<F>::T raw[4];
+        if (in) ldrow<F, 4>(M, row * ldm + kb, raw);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          da[4 * g + u] = in ? widen<F>(raw[u], mul) : 0.0;
+          db[4 * g + u] = (V && in) ? V[(kb + u) * vsk] : 0.0;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < MB; ++u) {
+        const int64_t k = kk + 4 * u + q;
+        const bool in = kk + 4 * u < k1;
+        da[u] = !in ? 0.0 : TRANS ? ldw<F>(M, row * ldm + k) : ldw<F>(M, k * ldm + row);
+        if constexpr (F == F8) da[u] *= mul;  // FP8 tiles hold codes of v 2^s
+        db[u] = (V && in) ? V[k * vsk] : 0.0;
+      }
     }
   };
   load(k0, a, b);
@@ -127,49 +180,43 @@ __device__ void tile_mfma_any(const void* M, int f, double mul, int nb, int r0, 
   }
 }
 
-// Raw storage element of a tile format and its widening to FP64: the wide
-// update loop holds its prefetched tile values in the storage width and widens
-// them at the MFMA, which keeps the narrow formats' register footprint small.
-template <int F> struct RawOf { using T = double; };
-template <> struct RawOf<F32> { using T = float; };
-template <> struct RawOf<F16> { using T = uint16_t; };
-template <> struct RawOf<BF16> { using T = uint16_t; };
-template <> struct RawOf<F8> { using T = uint8_t; };
-template <int F>
-__device__ __forceinline__ typename RawOf<F>::T ldraw(const void* p, int64_t i) {
-  return ((const typename RawOf<F>::T*)p)[i];
-}
-template <int F>
-__device__ __forceinline__ double widen(typename RawOf<F>::T v, double mul) {
-  if constexpr (F == F64) return v;
-  else if constexpr (F == F32) return (double)v;
-  else if constexpr (F == F16) return (double)f16_to_f32(v);
-  else if constexpr (F == BF16) return (double)bf16_to_f32(v);
-  else return (double)e4m3_to_f32(v) * mul;  // FP8 tiles hold codes of v 2^s
-}
-
 // Wide variant for the update launches with many tiles: one workgroup owns 64
 // output rows (four 16-row blocks that share each right-hand-side value it
 // loads), its SW4 waves split the contraction into equal parts.
 template <int F, bool TRANS>
 __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t row0, int k0, int k1, const double* V,
                                            int64_t vsk, int lane, d4 (&acc)[4], double mul) {
-  constexpr int U = 2;  // k4 steps per batch
+  // k4 steps per batch; the transposed loads take runs of U (one vector per
+  // row: 16 bytes for FP64, 8 for FP32 and the 16-bit formats, 4 for FP8)
+  constexpr int U = (TRANS && F != F64 && F != F32) ? 4 : 2;
   using RT = typename RawOf<F>::T;
   const int q = lane >> 4;
   RT a[4][U], an[4][U];
   double b[U], bn[U];
   auto load = [&](int kk, RT (*da)[U], double* db) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = kk + 4 * u + q;
-      const bool in = kk + 4 * u < k1;
+    if constexpr (TRANS) {
+      // group q takes the U consecutive k from kk + U q (k0, k1 multiples of 16)
+      const int64_t kb = kk + U * q;
+      const bool in = kb < k1;
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const int64_t row = row0 + 16 * h;
-        da[h][u] = !in ? RT(0) : TRANS ? ldraw<F>(M, row * ldm + k) : ldraw<F>(M, k * ldm + row);
+        if (in) ldrow<F, U>(M, (row0 + 16 * h) * ldm + kb, da[h]);
+        else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) da[h][u] = RT(0);
+        }
       }
-      db[u] = (V && in) ? V[k * vsk] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) db[u] = (V && in) ? V[(kb + u) * vsk] : 0.0;
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = kk + 4 * u + q;
+        const bool in = kk + 4 * u < k1;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) da[h][u] = !in ? RT(0) : ldraw<F>(M, k * ldm + row0 + 16 * h);
+        db[u] = (V && in) ? V[k * vsk] : 0.0;
+      }
     }
   };
   load(k0, a, b);
