@@ -1112,8 +1112,10 @@ __device__ __forceinline__ void mfma_rows16x32(const double* A, const double* B,
 // doubles of LDS per wave), and X is re-read by the same wave after a
 // workgroup-scope fence.
 // ---------------------------------------------------------------------------
+// rdiag (optional) holds 1 / L[r][r]; the substitution then multiplies instead
+// of dividing.
 __device__ __forceinline__ void invert_lower32(const double* L, int64_t ld, double* out, double (*W)[PW + 1],
-                                               int lane) {
+                                               int lane, const double* rdiag = nullptr) {
   for (int e = lane; e < PW * PW; e += 64) {
     const int r = e % PW, c = e / PW;
     W[r][c] = r >= c ? L[(int64_t)c * ld + r] : 0.0;
@@ -1125,8 +1127,8 @@ __device__ __forceinline__ void invert_lower32(const double* L, int64_t ld, doub
     for (int r = 0; r < PW; ++r) {
       double v = (r == lane) ? 1.0 : 0.0;
 #pragma unroll
-      for (int m = 0; m < r; ++m) v -= W[r][m] * y[m];
-      y[r] = v / W[r][r];
+      for (int m = 0; m < r; ++m) v = fma(-W[r][m], y[m], v);
+      y[r] = rdiag ? v * rdiag[r] : v / W[r][r];
     }
 #pragma unroll
     for (int r = 0; r < PW; ++r) out[lane * PW + r] = y[r];
@@ -1195,14 +1197,12 @@ __device__ __forceinline__ void trsm_rows16_inv(const double* X, const double* L
 // ---------------------------------------------------------------------------
 // Blocked POTRF of the FP64 diagonal tile k, spread over several workgroups:
 // the tile is split into SB x SB blocks and, for each block column j,
-//   (a) k_potrf_block  one workgroup factors the diagonal block D_jj
-//                      (left-looking over 16-column panels inside the block:
-//                      FP64 MFMA panel update, the 16 x 16 diagonal block by
-//                      one wave with lane broadcasts, rows below by
-//                      substitution; 16 columns keep the unrolled code small
-//                      enough to stay in the instruction cache),
-//                      It also inverts the four 32 x 32 diagonal blocks of
-//                      D_jj into dinv for the solves below,
+//   (a) k_potrf_block  one workgroup factors the diagonal block D_jj, held
+//                      in registers (right-looking over 16-column panels,
+//                      FP64 MFMA for the panel and trailing blocks, the
+//                      16 x 16 diagonal blocks by one wave with lane
+//                      broadcasts); it also inverts the four 32 x 32
+//                      diagonal blocks of D_jj into dinv for the solves below,
 //   (b) k_potrf_panel  the rows below solve X D_jj^T = A, one wave per 16
 //                      rows (trsm_rows16_inv),
 //   (c) k_potrf_syrk   the lower trailing part loses L_{:,j} L_{:,j}^T
@@ -1218,66 +1218,42 @@ __device__ __forceinline__ double readlane_f64(double v, int src) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// 1 / sqrt(d) for d > 0 (normal): the hardware estimate refined by three
+// Newton steps y <- y + (y / 2)(1 - d y^2), each of which squares the relative
+// error, so the result is within a few units in the last place.
+__device__ __forceinline__ double rsqrt_f64(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Unblocked Cholesky of an N x N block held one row per lane (lane r < N:
 // x[c] = D[r][c], c <= r), by one wave with lane broadcasts and no barriers.
-// Returns the first column whose pivot is not positive, or -1.
+// The pivot's reciprocal square root r_c gives both L[c][c] = d_c r_c and the
+// column below as multiplications (no divide on the column-to-column chain);
+// rdiag[c] receives r_c = 1 / L[c][c].  Returns the first column whose pivot
+// is not positive, or -1.
 template <int N>
-__device__ __forceinline__ int chol_wave(double (&x)[N], int lane) {
+__device__ __forceinline__ int chol_wave(double (&x)[N], int lane, double* rdiag) {
 #pragma unroll
   for (int c = 0; c < N; ++c) {
     const double d = readlane_f64(x[c], c);
     if (!(d > 0.0)) return c;
-    const double piv = sqrt(d);
-    const double lc = (lane == c) ? piv : x[c] / piv;
+    const double rs = rsqrt_f64(d);
+    if (lane == 0) rdiag[c] = rs;
+    const double lc = (lane == c) ? d * rs : x[c] * rs;
     x[c] = lc;
 #pragma unroll
     for (int q = c + 1; q < N; ++q) {
       const double lq = readlane_f64(lc, q);
-      if (lane >= q) x[q] -= lc * lq;
+      if (lane >= q) x[q] = fma(-lc, lq, x[q]);
     }
   }
   return -1;
-}
-
-// acc += A[R0 .. R0+15, K0:K1] * B[C0 .. C0+15, K0:K1]^T straight from
-// column-major FP64 storage (leading dimension ld), 16 k per batch with the
-// next batch's loads in flight.  K1 - K0 is a multiple of 4.
-__device__ __forceinline__ void mfma_rows16x16(const double* A, const double* B, int64_t ld, int R0, int C0, int K0,
-                                               int K1, int lane, d4& acc) {
-  const int r = lane & 15, q = lane >> 4;
-  int kk = K0;
-  const int full_end = K0 + ((K1 - K0) / 16) * 16;
-  if (kk < full_end) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = A[(int64_t)(kk + 4 * u + q) * ld + R0 + r];
-      b[u] = B[(int64_t)(kk + 4 * u + q) * ld + C0 + r];
-    }
-    for (; kk < full_end; kk += 16) {
-      double na[4], nb4[4];
-      const bool more = kk + 16 < full_end;
-      if (more) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          na[u] = A[(int64_t)(kk + 16 + 4 * u + q) * ld + R0 + r];
-          nb4[u] = B[(int64_t)(kk + 16 + 4 * u + q) * ld + C0 + r];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-      if (more) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a[u] = na[u];
-          b[u] = nb4[u];
-        }
-      }
-    }
-  }
-  for (; kk < K1; kk += 4)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(int64_t)(kk + q) * ld + R0 + r], B[(int64_t)(kk + q) * ld + C0 + r],
-                                               acc, 0, 0, 0);
 }
 
 // acc[h] += A[R0 .. R0+15, K0:K1] * B[C0 + 16h .. C0 + 16h + 15, K0:K1]^T, h < 4,
@@ -1318,80 +1294,176 @@ __device__ __forceinline__ void mfma_rows16x64(const double* A, const double* B,
 
 constexpr int PB = 16;  // panel width inside the diagonal block
 
+// The 36 lower 16 x 16 blocks (bi >= bj) of a 128 x 128 diagonal block, by
+// columns; block b belongs to wave b % 4 (its slot b / 4 of nine).
+constexpr int NBLK = (SB / PB) * (SB / PB + 1) / 2;
+__device__ __forceinline__ void blk_ij(int b, int& bi, int& bj) {
+  bj = 0;
+  int rem = b, len = SB / PB;
+  while (rem >= len) { rem -= len; ++bj; --len; }
+  bi = bj + rem;
+}
+
+// Register-resident right-looking factorisation of the diagonal block: every
+// wave holds its nine 16 x 16 blocks in the MFMA result layout for the whole
+// kernel (loaded once, stored once).  Per 16-column panel p:
+//   (1) the owner of block (p, p) factors it by one wave with lane broadcasts
+//       and inverts the 16 x 16 factor (forward substitution on unit vectors);
+//   (2) the owners of the blocks (i, p) below form L_ip = A_ip L_pp^{-T} (FP64
+//       MFMA, the block brought into the operand layout through LDS) and put
+//       L_ip in LDS;
+//   (3) every trailing block (i, j), p < j <= i, loses L_ip L_jp^T (FP64 MFMA
+//       from LDS).
+// Two barriers per panel; the panel's blocks pass through 16 x 17 LDS slots.
 __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j, double* dinv) {
   if (*tv.info) return;
   const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
   double* A = (double*)tv.tile(k, k);
-  __shared__ double D[PB][PB + 1];
+  __shared__ double Dg[PB][PB + 1];  // the diagonal block, then its factor
+  __shared__ double Di[PB][PB + 1];  // the factor's inverse
+  __shared__ double Dr[SB];          // 1 / L[c][c] of the block's columns
+  // panel blocks P[i] (16 x 17 each), later the waves' 32 x 32 inversion space
+  constexpr int PSZ = (SB / PB) * PB * (PB + 1);
+  constexpr int WSZ = 4 * PW * (PW + 1);
+  __shared__ double pool[PSZ > WSZ ? PSZ : WSZ];
+  double (*P)[PB][PB + 1] = (double (*)[PB][PB + 1])pool;
   __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane >> 4, lc = lane & 15;  // result layout: rows lr + 4 r, column lc
   if (tid == 0) fail = 0;
-#pragma unroll 1
-  for (int J0 = c0; J0 < c1; J0 += PB) {
-    // (1) A[J0:c1, J] -= L[J0:c1, c0:J0] L[J, c0:J0]^T, 16-row blocks over the 4 waves
-    if (J0 > c0) {
-      for (int rb = wave; rb < (c1 - J0) / 16; rb += 4) {
-        const int R0 = J0 + rb * 16;
-        d4 acc = {0, 0, 0, 0};
-        mfma_rows16x16(A, A, nb, R0, J0, c0, J0, lane, acc);
+
+  d4 acc[9];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int R = R0 + (lane >> 4) + 4 * r, c = lane & 15;
-          if (R >= J0 + c) A[(int64_t)(J0 + c) * nb + R] -= acc[r];
-        }
-      }
-      __syncthreads();
+  for (int sl = 0; sl < 9; ++sl) {
+    const int b = 4 * sl + wave;
+    acc[sl] = d4{0, 0, 0, 0};
+    if (b < NBLK) {
+      int bi, bj;
+      blk_ij(b, bi, bj);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc[sl][r] = A[(int64_t)(c0 + PB * bj + lc) * nb + c0 + PB * bi + lr + 4 * r];
     }
-    // (2) the 16 x 16 diagonal block, one wave
-    if (wave == 0) {
+  }
+  __syncthreads();
+
+#pragma unroll 1
+  for (int p = 0; p < SB / PB; ++p) {
+    // (1) diagonal block (p, p), block index 8p - p(p-1)/2; the factorisation
+    // code is outside the slot loop so that it exists once in the kernel
+    const int bpp = (SB / PB) * p - p * (p - 1) / 2;
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl)
+      if (4 * sl + wave == bpp) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Dg[lr + 4 * r][lc] = acc[sl][r];
+      }
+    if (wave == bpp % 4) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       double x[PB];
 #pragma unroll
-      for (int c = 0; c < PB; ++c)
-        x[c] = (lane < PB && c <= lane) ? A[(int64_t)(J0 + c) * nb + J0 + lane] : 0.0;
-      const int bad = chol_wave<PB>(x, lane);
+      for (int c = 0; c < PB; ++c) x[c] = (lane < PB && c <= lane) ? Dg[lane][c] : 0.0;
+      const int bad = chol_wave<PB>(x, lane, Dr + PB * p);
       if (bad >= 0) {
         if (lane == 0) {
           fail = 1;
-          if (*tv.info == 0) *tv.info = k * nb + J0 + bad + 1;
+          if (*tv.info == 0) *tv.info = k * nb + c0 + PB * p + bad + 1;
         }
-      } else if (lane < PB) {
+      } else {
+        if (lane < PB) {
 #pragma unroll
-        for (int c = 0; c < PB; ++c) {
-          const double v = c <= lane ? x[c] : 0.0;
-          D[lane][c] = v;
-          if (c <= lane) A[(int64_t)(J0 + c) * nb + J0 + lane] = v;
+          for (int c = 0; c < PB; ++c) Dg[lane][c] = c <= lane ? x[c] : 0.0;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < PB) {  // column lane of the inverse
+          double y[PB];
+#pragma unroll
+          for (int r = 0; r < PB; ++r) {
+            double v = (r == lane) ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = 0; m < r; ++m) v = fma(-Dg[r][m], y[m], v);
+            y[r] = v * Dr[PB * p + r];
+          }
+#pragma unroll
+          for (int r = 0; r < PB; ++r) Di[r][lane] = y[r];
+        }
+#pragma unroll
+        for (int sl = 0; sl < 9; ++sl)
+          if (4 * sl + wave == bpp) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[sl][r] = Dg[lr + 4 * r][lc];
+          }
       }
     }
     __syncthreads();
     if (fail) return;
-    // (3) rows J0+16 .. c1 of the block (fewer than SB): x L_JJ^T = a, one row per thread
-    if (tid < c1 - J0 - PB) {
-      const int R = J0 + PB + tid;
-      double x[PB];
+    // (2) panel blocks (i, p), i > p
 #pragma unroll
-      for (int c = 0; c < PB; ++c) x[c] = A[(int64_t)(J0 + c) * nb + R];
+    for (int sl = 0; sl < 9; ++sl) {
+      const int b = 4 * sl + wave;
+      if (b >= NBLK) continue;
+      int bi, bj;
+      blk_ij(b, bi, bj);
+      if (bj != p || bi == p) continue;
 #pragma unroll
-      for (int c = 0; c < PB; ++c) {
-        double v = x[c];
+      for (int r = 0; r < 4; ++r) P[bi][lr + 4 * r][lc] = acc[sl][r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      d4 xv = {0, 0, 0, 0};
 #pragma unroll
-        for (int m = 0; m < c; ++m) v -= x[m] * D[c][m];
-        x[c] = v / D[c][c];
-      }
+      for (int u = 0; u < 4; ++u)
+        xv = __builtin_amdgcn_mfma_f64_16x16x4f64(P[bi][lc][4 * u + lr], Di[lc][4 * u + lr], xv, 0, 0, 0);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      acc[sl] = xv;
 #pragma unroll
-      for (int c = 0; c < PB; ++c) A[(int64_t)(J0 + c) * nb + R] = x[c];
+      for (int r = 0; r < 4; ++r) P[bi][lr + 4 * r][lc] = xv[r];
     }
     __syncthreads();
+    // (3) trailing blocks (i, j), p < j <= i
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl) {
+      const int b = 4 * sl + wave;
+      if (b >= NBLK) continue;
+      int bi, bj;
+      blk_ij(b, bi, bj);
+      if (bj <= p) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(-P[bi][lc][4 * u + lr], P[bj][lc][4 * u + lr], acc[sl], 0,
+                                                       0, 0);
+    }
   }
-  // the strictly upper part of columns c0 .. c1 is zero in the factor
-  for (int e = tid; e < SB * c1; e += 256) {
-    const int r = e % c1, c = c0 + e / c1;
-    if (r < c) A[(int64_t)c * nb + r] = 0.0;
+
+  // the factor's lower blocks, then zeros above the diagonal in columns c0 .. c1
+#pragma unroll
+  for (int sl = 0; sl < 9; ++sl) {
+    const int b = 4 * sl + wave;
+    if (b >= NBLK) continue;
+    int bi, bj;
+    blk_ij(b, bi, bj);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (bi > bj || lr + 4 * r >= lc) A[(int64_t)(c0 + PB * bj + lc) * nb + c0 + PB * bi + lr + 4 * r] = acc[sl][r];
   }
+  // (one wave per column, two rows per lane and store)
+  for (int c = c0 + wave; c < c1; c += 4)
+    for (int r = 2 * lane; r < c; r += 128) {
+      double* o = A + (int64_t)c * nb + r;
+      if (r + 1 < c) *(double2*)o = double2{0.0, 0.0};
+      else *o = 0.0;
+    }
+  __syncthreads();
   // inverses of the four 32 x 32 diagonal blocks, one per wave
-  __shared__ double W[4][PW][PW + 1];
+  double (*W)[PW][PW + 1] = (double (*)[PW][PW + 1])pool;
   const int d0 = c0 + wave * PW;
-  invert_lower32(A + (int64_t)d0 * nb + d0, nb, dinv + (int64_t)d0 * PW, W[wave], lane);
+  invert_lower32(A + (int64_t)d0 * nb + d0, nb, dinv + (int64_t)d0 * PW, W[wave], lane, Dr + wave * PW);
 }
 
 // rows c1 .. nb of block column j: X D_jj^T = A in place, one wave per 16 rows

@@ -188,7 +188,7 @@ __device__ __forceinline__ void mfma_span4(const void* M, int64_t ldm, int64_t r
                                            int64_t vsk, int lane, d4 (&acc)[4], double mul) {
   // k4 steps per batch; the transposed loads take runs of U (one vector per
   // row: 16 bytes for FP64, 8 for FP32 and the 16-bit formats, 4 for FP8)
-  constexpr int U = (TRANS && F != F64 && F != F32) ? 4 : 2;
+  constexpr int U = (F == F64 || (TRANS && F == F32)) ? 2 : 4;
   using RT = typename RawOf<F>::T;
   const int q = lane >> 4;
   RT a[4][U], an[4][U];
