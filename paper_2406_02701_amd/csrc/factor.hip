@@ -1593,11 +1593,86 @@ __global__ __launch_bounds__(256) void k_quant_panel_f8(TileView tv, int k, cons
   if (threadIdx.x == 0) tv.sc[tri_index(ti, k)] = (int8_t)sc;
 }
 
+// The same panel solve with four waves per 16 rows, for steps with few panel
+// tiles, where the solve sits alone on the critical path: the update of every
+// 32-column chunk is split over the waves by quarters of its contraction
+// (their partial products added in wave order through LDS), and wave 0 forms
+// the chunk's columns with the inverted diagonal block.  Two barriers per
+// chunk; the chunk's columns reach the other waves through global memory
+// after a workgroup-scope fence.
+constexpr int TRSM_SPLIT_MAX = 16;  // panel tiles up to which the split solve is used
+
+__global__ __launch_bounds__(256) void k_trsm4(TileView tv, int k, double* ws, const double* dinv) {
+  if (*tv.info) return;
+  const int nb = tv.nb, rblocks = nb / 16;
+  const int ti = k + 1 + blockIdx.x / rblocks;
+  const int r0 = (blockIdx.x % rblocks) * 16;
+  void* Ap = tv.tile(ti, k);
+  const int fa = tv.tfmt(ti, k);
+  const double ma = tv.tmul(ti, k);
+  double* X = ws + (int64_t)(ti - k - 1) * nb * nb;
+  const double* L = (const double*)tv.tile(k, k);
+  __shared__ double red[4][16][PW + 1];
+  __shared__ double Ts[16][PW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = lane >> 4, c = lane & 15;
+#pragma unroll 1
+  for (int J0 = 0; J0 < nb; J0 += PW) {
+    const int part = J0 / 4;  // a multiple of 8
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    mfma_rows16x32(X, L, nb, r0, J0, w * part, (w + 1) * part, lane, acc0, acc1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[w][q + 4 * r][c] = acc0[r];
+      red[w][q + 4 * r][c + 16] = acc1[r];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int R = q + 4 * r;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int cc = c + 16 * h;
+          const double a = load_wide(Ap, fa, (int64_t)(J0 + cc) * nb + r0 + R) * ma;
+          Ts[R][cc] = a - (((red[0][R][cc] + red[1][R][cc]) + red[2][R][cc]) + red[3][R][cc]);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      const double* Di = dinv + (int64_t)(J0 / PW) * PW * PW;  // Di[kk * 32 + n] = D_J^{-1}[n][kk]
+      d4 x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < PW / 4; ++u) {
+        const int kk = 4 * u + q;
+        const double a = Ts[c][kk];
+        x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Di[kk * PW + c], x0, 0, 0, 0);
+        x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Di[kk * PW + 16 + c], x1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i0 = (int64_t)(J0 + c) * nb + r0 + q + 4 * r;
+        X[i0] = x0[r];
+        X[i0 + 16 * nb] = x1[r];
+        // FP8 tiles are rounded by k_quant_panel_f8 once the whole tile's largest magnitude is known
+        if (fa != F8) {
+          store_round(Ap, fa, i0, x0[r]);
+          store_round(Ap, fa, i0 + 16 * nb, x1[r]);
+        }
+      }
+      __threadfence_block();
+    }
+    __syncthreads();
+  }
+}
+
 hipError_t launch_trsm_panel(const TileView& tv, int k, double* ws, const double* dinv, bool fp8_panel,
                              hipStream_t s) {
   int ntile = tv.nt - k - 1;
   if (ntile <= 0) return hipSuccess;
-  k_trsm<<<ntile * (tv.nb / 16), 64, 0, s>>>(tv, k, ws, dinv);
+  if (ntile <= TRSM_SPLIT_MAX)
+    k_trsm4<<<ntile * (tv.nb / 16), 256, 0, s>>>(tv, k, ws, dinv);
+  else
+    k_trsm<<<ntile * (tv.nb / 16), 64, 0, s>>>(tv, k, ws, dinv);
   if (fp8_panel) k_quant_panel_f8<<<ntile, 256, 0, s>>>(tv, k, ws);
   return hipGetLastError();
 }
