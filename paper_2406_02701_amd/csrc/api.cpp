@@ -517,10 +517,13 @@ int run_factorisation(mpcr_ctx* ctx, mpcr_factor* f) {
       HIP_TRY(ctx, launch_pack_split(tv, (int)k, o3, ob, P));
     }
     HIP_TRY(ctx, hipEventRecord(ev(2 * k), P));
-    if (k > 0) {  // U and U2 finished step k-1
-      HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));
-      HIP_TRY(ctx, hipStreamWaitEvent(P, ev2(k - 1), 0));
-    }
+    // P next updates the diagonal tile (k+1, k+1), last written by U in step
+    // k-1 (diagonal tiles are FP64).  It does not wait for U2: the FP32 and
+    // lower tiles of step k-1 matter to P only from TRSM(k+1) on (the panel
+    // tiles, and the split-panel buffer that pack(k+1) rewrites), and C, which
+    // P waits for before TRSM(k+1), has waited for U2.  POTRF(k+1) thus
+    // overlaps the tail of step k-1's lower-format update.
+    if (k > 0) HIP_TRY(ctx, hipStreamWaitEvent(P, ev(2 * (k - 1) + 1), 0));
     if ((rc = launch_updates(k, P, 0)) != MPCR_OK) return rc;
     HIP_TRY(ctx, hipStreamWaitEvent(C, ev(2 * k), 0));
     if (k > 0) {
