@@ -1502,9 +1502,12 @@ __global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
 
 // A_jj -= L_jk L_jk^T for one diagonal tile with an FP64 panel tile (the SYRK
 // on the factorisation's critical path): one workgroup per lower 64 x 64 block,
-// wave w: rows 16w .. 16w+15 of the block in one pass over k, FP64 MFMA
-// straight from the tiles.
-__global__ __launch_bounds__(256) void k_syrk_tile(TileView tv, int k, int j) {
+// eight waves: wave w takes rows 16 (w % 4) .. of the block over one half of
+// the contraction (FP64 MFMA straight from the tiles); the second half's
+// partial products are added to the first's through LDS.  Halving each wave's
+// chain of dependent MFMAs halves the kernel's latency, which is what counts
+// here: the 36 workgroups of a 512-tile occupy few CUs.
+__global__ __launch_bounds__(512) void k_syrk_tile(TileView tv, int k, int j) {
   if (*tv.info) return;
   const int nb = tv.nb;
   int bi = 0, rem = blockIdx.x;
@@ -1513,23 +1516,34 @@ __global__ __launch_bounds__(256) void k_syrk_tile(TileView tv, int k, int j) {
   const double* L = (const double*)tv.tile(j, k);
   double* A = (double*)tv.tile(j, j);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R0 = bi * 64 + wave * 16, C0 = bj * 64;
+  const int rg = wave & 3, kh = wave >> 2, kw = nb / 2;
+  const int R0 = bi * 64 + rg * 16, C0 = bj * 64;
+  __shared__ double red[4][16][65];
   d4 acc[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) acc[h] = d4{0, 0, 0, 0};
-  mfma_rows16x64(L, L, nb, R0, C0, 0, nb, lane, acc);
+  mfma_rows16x64(L, L, nb, R0, C0, kh * kw, (kh + 1) * kw, lane, acc);
+  if (kh == 1) {
 #pragma unroll
-  for (int h = 0; h < 4; ++h)
+    for (int h = 0; h < 4; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 16 * h + (lane & 15);
-      if (R >= C) A[(int64_t)C * nb + R] -= acc[h][r];
-    }
+      for (int r = 0; r < 4; ++r) red[rg][(lane >> 4) + 4 * r][16 * h + (lane & 15)] = acc[h][r];
+  }
+  __syncthreads();
+  if (kh == 0) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 16 * h + (lane & 15);
+        if (R >= C) A[(int64_t)C * nb + R] -= acc[h][r] + red[rg][(lane >> 4) + 4 * r][16 * h + (lane & 15)];
+      }
+  }
 }
 
 hipError_t launch_syrk_tile(const TileView& tv, int k, int j, hipStream_t s) {
   const int nbk = tv.nb / 64;
-  k_syrk_tile<<<nbk * (nbk + 1) / 2, 256, 0, s>>>(tv, k, j);
+  k_syrk_tile<<<nbk * (nbk + 1) / 2, 512, 0, s>>>(tv, k, j);
   return hipGetLastError();
 }
 
