@@ -1614,7 +1614,7 @@ __global__ __launch_bounds__(256) void k_quant_panel_f8(TileView tv, int k, cons
 // the chunk's columns with the inverted diagonal block.  Two barriers per
 // chunk; the chunk's columns reach the other waves through global memory
 // after a workgroup-scope fence.
-constexpr int TRSM_SPLIT_MAX = 16;  // panel tiles up to which the split solve is used
+constexpr int TRSM_SPLIT_MAX = 32;  // panel tiles up to which the split solve is used
 
 __global__ __launch_bounds__(256) void k_trsm4(TileView tv, int k, double* ws, const double* dinv) {
   if (*tv.info) return;
