@@ -1442,16 +1442,41 @@ __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j, 
     }
   }
 
-  // the factor's lower blocks, then zeros above the diagonal in columns c0 .. c1
+  // the factor's lower blocks, each turned through a 16 x 17 LDS slot of its
+  // wave so that a lane stores four consecutive rows of one column (a store
+  // instruction then covers whole 128-byte pieces of 16 columns), then zeros
+  // above the diagonal in columns c0 .. c1
+  __syncthreads();  // the panel slots are free once every wave has left (3)
+  {
+    double (*T)[PB + 1] = (double (*)[PB + 1])(pool + wave * PB * (PB + 1));
+    const int tc = lane >> 2, tr = 4 * (lane & 3);
 #pragma unroll
-  for (int sl = 0; sl < 9; ++sl) {
-    const int b = 4 * sl + wave;
-    if (b >= NBLK) continue;
-    int bi, bj;
-    blk_ij(b, bi, bj);
+    for (int sl = 0; sl < 9; ++sl) {
+      const int b = 4 * sl + wave;
+      if (b >= NBLK) continue;
+      int bi, bj;
+      blk_ij(b, bi, bj);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (bi > bj || lr + 4 * r >= lc) A[(int64_t)(c0 + PB * bj + lc) * nb + c0 + PB * bi + lr + 4 * r] = acc[sl][r];
+      for (int r = 0; r < 4; ++r) T[lr + 4 * r][lc] = acc[sl][r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = T[tr + e][tc];
+      double* o = A + (int64_t)(c0 + PB * bj + tc) * nb + c0 + PB * bi + tr;
+      if (bi > bj) {
+        *(double2*)o = double2{v[0], v[1]};
+        *(double2*)(o + 2) = double2{v[2], v[3]};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (tr + e >= tc) o[e] = v[e];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
   // (one wave per column, two rows per lane and store)
   for (int c = c0 + wave; c < c1; c += 4)
