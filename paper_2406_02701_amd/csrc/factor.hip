@@ -1323,7 +1323,8 @@ __global__ __launch_bounds__(256) void k_potrf_block(TileView tv, int k, int j, 
   __shared__ double Dg[PB][PB + 1];  // the diagonal block, then its factor
   __shared__ double Di[PB][PB + 1];  // the factor's inverse
   __shared__ double Dr[SB];          // 1 / L[c][c] of the block's columns
-  // panel blocks P[i] (16 x 17 each), later the waves' 32 x 32 inversion space
+  // panel blocks P[i] (16 x 17 each), later the waves' store slots and 32 x 32
+  // inversion space
   constexpr int PSZ = (SB / PB) * PB * (PB + 1);
   constexpr int WSZ = 4 * PW * (PW + 1);
   __shared__ double pool[PSZ > WSZ ? PSZ : WSZ];
@@ -1503,8 +1504,11 @@ __global__ __launch_bounds__(64) void k_potrf_panel(TileView tv, int k, int j, c
 }
 
 // A[R, C] -= L[R, c0:c1] L[C, c0:c1]^T for c1 <= C <= R < nb; one workgroup per
-// lower 64 x 64 block (bi >= bj), wave w: rows 16w .. 16w+15 of the block
-__global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
+// lower 64 x 64 block (bi >= bj), eight waves: wave w takes rows 16 (w % 4) ..
+// of the block over one half of the 128 columns, and the second half's partial
+// products are added to the first's through LDS (half the chain of dependent
+// loads and MFMAs per wave on this critical-path step)
+__global__ __launch_bounds__(512) void k_potrf_syrk(TileView tv, int k, int j) {
   if (*tv.info) return;
   const int nb = tv.nb, c0 = j * SB, c1 = c0 + SB;
   double* A = (double*)tv.tile(k, k);
@@ -1512,18 +1516,29 @@ __global__ __launch_bounds__(256) void k_potrf_syrk(TileView tv, int k, int j) {
   while (rem > bi) { rem -= bi + 1; ++bi; }
   const int bj = rem;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R0 = c1 + bi * 64 + wave * 16, C0 = c1 + bj * 64;
+  const int rg = wave & 3, kh = wave >> 2, kw = SB / 2;
+  const int R0 = c1 + bi * 64 + rg * 16, C0 = c1 + bj * 64;
+  __shared__ double red[4][16][65];
   d4 acc[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) acc[h] = d4{0, 0, 0, 0};
-  mfma_rows16x64(A, A, nb, R0, C0, c0, c1, lane, acc);
+  mfma_rows16x64(A, A, nb, R0, C0, c0 + kh * kw, c0 + (kh + 1) * kw, lane, acc);
+  if (kh == 1) {
 #pragma unroll
-  for (int h = 0; h < 4; ++h)
+    for (int h = 0; h < 4; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 16 * h + (lane & 15);
-      if (R >= C) A[(int64_t)C * nb + R] -= acc[h][r];
-    }
+      for (int r = 0; r < 4; ++r) red[rg][(lane >> 4) + 4 * r][16 * h + (lane & 15)] = acc[h][r];
+  }
+  __syncthreads();
+  if (kh == 0) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int R = R0 + (lane >> 4) + 4 * r, C = C0 + 16 * h + (lane & 15);
+        if (R >= C) A[(int64_t)C * nb + R] -= acc[h][r] + red[rg][(lane >> 4) + 4 * r][16 * h + (lane & 15)];
+      }
+  }
 }
 
 // A_jj -= L_jk L_jk^T for one diagonal tile with an FP64 panel tile (the SYRK
@@ -1580,7 +1595,7 @@ hipError_t launch_potrf_tile(const TileView& tv, int k, double* dinv, hipStream_
     const int rest = (tv.nb - (j + 1) * SB) / 64;  // 64-row blocks below block j
     if (rest > 0) {
       k_potrf_panel<<<rest * 4, 64, 0, s>>>(tv, k, j, dinv);
-      k_potrf_syrk<<<rest * (rest + 1) / 2, 256, 0, s>>>(tv, k, j);
+      k_potrf_syrk<<<rest * (rest + 1) / 2, 512, 0, s>>>(tv, k, j);
     }
   }
   return hipGetLastError();
